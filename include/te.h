@@ -1,0 +1,152 @@
+/*
+ * te.h -- C interface of libte, ensemble transfer entropy (KSG estimator) on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library estimates TE_SPO(X -> Y, t, u) = I(Y_t ; X^{d_x}_{t-u} | Y^{d_y}_{t-1})
+ * (Wollstadt et al. 2014, eq. 3) for every analysis time point of an ensemble
+ * of repetitions (Background, eq. 1-2), with the ensemble KSG estimator of
+ * eq. 9, pooled over a window of samples as in eq. 10, and tests it against
+ * repetition-shuffled surrogates (Fig. 3; "TE calculation and statistical
+ * testing against surrogate data").
+ *
+ * Conventions for every entry point
+ *   - Return value: te_status.  TE_OK on success; otherwise te_last_error()
+ *     returns a message for the calling thread.  No exception crosses the ABI.
+ *   - "device" pointers are HIP device (HBM) addresses; "host" pointers are
+ *     ordinary process memory.  The caller owns every buffer it passes in and
+ *     keeps it alive until the call returns (or, for te_serve_submit, as stated
+ *     there).  The library allocates no device memory on these paths: all
+ *     device scratch space lives in the caller's workspace.
+ *   - hip_stream is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *     their work on it; calls that write host outputs synchronise the stream
+ *     before they return.
+ *   - Series are float32, laid out [n_pairs][n_trials][n_samples] row-major:
+ *     element (p, r, t) is the observation at sample t of repetition r of
+ *     pair p.  Values must be finite: a NaN or Inf met while embedding makes
+ *     the call return TE_ERR_INVALID (outputs are then NaN).
+ *
+ * Semantics fixed by the library (readings of points the paper leaves open)
+ *   - embedding (eq. 6-7 and the remark that the source is embedded the same
+ *     way at t-u): the point of repetition r at sample t' is
+ *     ( y_t' | y_{t'-1}, y_{t'-1-tau}, ..., y_{t'-1-(d_y-1)tau}
+ *            | x_{t'-u}, x_{t'-u-tau}, ..., x_{t'-u-(d_x-1)tau} );
+ *   - a window pools repetitions r < R_c and samples t' in [w_c, w_c + W_c)
+ *     (eq. 10), R_c * W_c points;
+ *   - distances are max-norms of IEEE binary32 round-to-nearest-even
+ *     coordinate differences; eps_i is the k-th smallest joint distance over
+ *     j != i (self excluded by index); counts are strict (< eps_i) in the
+ *     spaces (y_t', Y_past), (Y_past) and (Y_past, X_past) of eq. 8;
+ *   - TE is in nats; surrogates permute the repetitions of the source block
+ *     (the same point set as permuting the target with the inverse
+ *     permutation); p = #{surrogates with TE >= original TE} / S.
+ */
+#ifndef TE_H
+#define TE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TE_OK = 0,
+    TE_ERR_INVALID = 1,    /* bad argument, geometry or non-finite input        */
+    TE_ERR_NOMEM = 2,      /* workspace / arena too small for the smallest unit  */
+    TE_ERR_DEVICE = 3,     /* HIP runtime error (message in te_last_error)       */
+    TE_ERR_BUSY = 4,       /* server queue full                                  */
+    TE_ERR_TIMEOUT = 5,    /* te_serve_wait timed out                            */
+    TE_ERR_CANCELLED = 6   /* ticket cancelled or server closed                  */
+} te_status;
+
+typedef struct te_plan_s *te_plan;       /* immutable after creation; caller destroys */
+typedef struct te_server_s *te_server;   /* caller closes                             */
+
+/* One analysis job: n_pairs source/target pairs, each an ensemble of
+ * n_trials repetitions of n_samples samples, analysed at n_points windows
+ * (eq. 10), with n_surrogates shuffled surrogates per (pair, point).
+ * The arrays are copied by te_plan_create. */
+typedef struct {
+    int32_t n_pairs, n_trials, n_samples;
+    int32_t d_y, d_x;          /* embedding dimensions, 1..4 each (eq. 6)          */
+    int32_t tau;               /* embedding delay >= 1 (eq. 6)                      */
+    int32_t u;                 /* assumed interaction delay >= 1 (eq. 3)            */
+    int32_t k;                 /* neighbours in the joint space, 1..15 (eq. 9)     */
+    int32_t n_points;          /* analysis windows                                  */
+    int32_t window;            /* W for every window when window_len is NULL        */
+    const int32_t *window_start;   /* host [n_points]: first sample w_c (0-based)  */
+    const int32_t *window_len;     /* host [n_points] or NULL: W_c                  */
+    const int32_t *trials;         /* host [n_points] or NULL: R_c (first R_c used) */
+    int32_t n_surrogates;      /* S >= 0                                            */
+} te_problem;
+
+/* Library version string. */
+const char *te_version(void);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *te_last_error(void);
+
+/* Validate a problem and precompute its geometry, chunk sizes and schedule.
+ * TE_ERR_INVALID if a dimension is out of range, a window lacks history
+ * (w_c < max(1+(d_y-1)tau, u+(d_x-1)tau)) or runs past n_samples, or a window
+ * pools N_c = R_c W_c <= k points.  The plan is read-only afterwards and may be
+ * used from several threads, each with its own workspace and stream. */
+te_status te_plan_create(const te_problem *problem, te_plan *out);
+te_status te_plan_destroy(te_plan plan);
+
+/* Device workspace sizes in bytes.  full: te_surrogates in a single batch;
+ * minimum: the smallest workspace te_surrogates accepts (it then splits the
+ * batch into several launches, with identical results); plain: what
+ * te_estimate needs. */
+te_status te_plan_workspace_bytes(te_plan plan, size_t *full, size_t *minimum, size_t *plain);
+
+/* Plain per-time-point path: the original (unshuffled) estimate of every
+ * (pair, point), one window at a time (embed, search, reduce per window).
+ *   x, y     device float32 [n_pairs][n_trials][n_samples] source / target
+ *   ws       device workspace of ws_bytes >= plain bytes
+ *   te_out   host float64 [n_pairs][n_points], nats */
+te_status te_estimate(te_plan plan, const float *x, const float *y,
+                      void *ws, size_t ws_bytes, void *hip_stream, double *te_out);
+
+/* Batched path: originals and all surrogates of every (pair, point) through
+ * one persistent search launch per batch (eq. 9-10, surrogate test).
+ *   perms    device int32 [n_pairs][n_points][n_surrogates][n_trials]: the
+ *            source block of repetition r in surrogate s is read from
+ *            repetition perms[p][c][s][r]; entries r < R_c must be a
+ *            permutation of 0..R_c-1 (checked: TE_ERR_INVALID otherwise).
+ *            May be NULL when n_surrogates == 0.
+ *   ws       device workspace of ws_bytes >= minimum bytes
+ *   te_orig  host float64 [n_pairs][n_points]
+ *   te_surr  host float64 [n_pairs][n_points][n_surrogates] (NULL if S == 0)
+ *   p_value  host float64 [n_pairs][n_points] (NaN if S == 0; may be NULL)
+ *   use_graph  nonzero: capture the batch in a hipGraph on first use and
+ *            replay it on later calls with the same pointers and stream. */
+te_status te_surrogates(te_plan plan, const float *x, const float *y, const int32_t *perms,
+                        void *ws, size_t ws_bytes, void *hip_stream, int32_t use_graph,
+                        double *te_orig, double *te_surr, double *p_value);
+
+/* Kernel-level export in the shape of the paper's neighbour-search call
+ * ("Input data"; "Implementation interface"): several pre-embedded chunks
+ * searched in one launch.
+ *   pts        device float32, coordinate-major: coordinate m of global point
+ *              i is pts[m * dim_stride + i]; coordinates ordered
+ *              (y_t | Y_past (d_y) | X_past (d_x))
+ *   offsets    host int64 [n_chunks + 1]: chunk c holds points
+ *              [offsets[c], offsets[c+1]); each chunk needs more than k points
+ *   ws         device workspace of te_knn_counts_workspace_bytes(n_chunks) bytes
+ *   eps        device float32 [offsets[n_chunks]]: radius of every point
+ *   counts     device int32 [3][offsets[n_chunks]]: n_P, n_TP, n_PS of every
+ *              point (counts[s * offsets[n_chunks] + i])
+ *   te_out     host float64 [n_chunks] or NULL: eq. 9 from those counts */
+size_t te_knn_counts_workspace_bytes(int32_t n_chunks, int64_t n_points_total);
+te_status te_knn_counts(const float *pts, int64_t dim_stride, const int64_t *offsets,
+                        int32_t n_chunks, int32_t d_y, int32_t d_x, int32_t k,
+                        void *ws, size_t ws_bytes, void *hip_stream,
+                        float *eps, int32_t *counts, double *te_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TE_H */

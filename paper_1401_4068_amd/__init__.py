@@ -1,0 +1,10 @@
+"""Ensemble transfer entropy (KSG estimator) on AMD MI355X: Python binding of libte.
+
+The computation runs in libte.so (HIP kernels for gfx950 behind the C interface
+in include/te.h).  This package only marshals arguments; PyTorch supplies
+device memory and streams.
+"""
+from ._lib import LIB_PATH, TEError, lib
+from .api import Plan, knn_counts, version
+
+__all__ = ["LIB_PATH", "Plan", "TEError", "knn_counts", "lib", "version"]

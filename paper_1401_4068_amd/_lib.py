@@ -1,0 +1,73 @@
+"""ctypes declarations of libte.so (include/te.h).  Loading fails loudly when the
+library has not been built; there is no fallback implementation."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libte.so")
+
+TE_OK, TE_ERR_INVALID, TE_ERR_NOMEM, TE_ERR_DEVICE, TE_ERR_BUSY, TE_ERR_TIMEOUT, TE_ERR_CANCELLED = range(7)
+STATUS_NAMES = {0: "TE_OK", 1: "TE_ERR_INVALID", 2: "TE_ERR_NOMEM", 3: "TE_ERR_DEVICE", 4: "TE_ERR_BUSY",
+                5: "TE_ERR_TIMEOUT", 6: "TE_ERR_CANCELLED"}
+
+
+class TEError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("n_pairs", ctypes.c_int32), ("n_trials", ctypes.c_int32), ("n_samples", ctypes.c_int32),
+        ("d_y", ctypes.c_int32), ("d_x", ctypes.c_int32), ("tau", ctypes.c_int32), ("u", ctypes.c_int32),
+        ("k", ctypes.c_int32), ("n_points", ctypes.c_int32), ("window", ctypes.c_int32),
+        ("window_start", ctypes.POINTER(ctypes.c_int32)), ("window_len", ctypes.POINTER(ctypes.c_int32)),
+        ("trials", ctypes.POINTER(ctypes.c_int32)), ("n_surrogates", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_st = ctypes.c_int
+_dp = ctypes.POINTER(ctypes.c_double)
+_szp = ctypes.POINTER(ctypes.c_size_t)
+
+SIGNATURES = {
+    "te_version": ([], ctypes.c_char_p),
+    "te_last_error": ([], ctypes.c_char_p),
+    "te_plan_create": ([ctypes.POINTER(Problem), ctypes.POINTER(_vp)], _st),
+    "te_plan_destroy": ([_vp], _st),
+    "te_plan_workspace_bytes": ([_vp, _szp, _szp, _szp], _st),
+    "te_estimate": ([_vp, _vp, _vp, _vp, _sz, _vp, _dp], _st),
+    "te_surrogates": ([_vp, _vp, _vp, _vp, _vp, _sz, _vp, _i32, _dp, _dp, _dp], _st),
+    "te_knn_counts_workspace_bytes": ([_i32, _i64], _sz),
+    "te_knn_counts": ([_vp, _i64, ctypes.POINTER(_i64), _i32, _i32, _i32, _i32, _vp, _sz, _vp, _vp, _vp, _dp], _st),
+}
+
+
+def lib():
+    """The loaded libte.so.  Raises if it is missing: build it with __graft_entry__.build()."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libte.so is not built (expected at %s); run `python -c \"import "
+                               "__graft_entry__ as g; g.build()\"`" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def check(status: int):
+    if status != TE_OK:
+        raise TEError(status, lib().te_last_error().decode(errors="replace"))

@@ -1,0 +1,187 @@
+"""Python front end of libte: argument marshalling only.
+
+PyTorch provides device memory (workspaces, inputs, outputs) and streams;
+every step of the computation runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from ._lib import Problem, check, lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    cur = torch.cuda.current_stream()
+    if stream is None:
+        stream = cur
+    elif stream != cur:
+        stream.wait_stream(cur)      # inputs written on the current stream are visible
+    return ctypes.c_void_p(stream.cuda_stream), stream
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Plan:
+    """An analysis plan (te_plan): geometry of one job, validated on creation.
+
+    Parameters follow te_problem in include/te.h: series of n_pairs pairs,
+    n_trials repetitions and n_samples samples; embedding d_y, d_x, tau; delay
+    u; k neighbours; per analysis point the window start, length and number of
+    pooled repetitions; n_surrogates shuffled surrogates.
+    """
+
+    def __init__(self, n_pairs, n_trials, n_samples, d_y, d_x, tau, u, k, window_start, window_len=None,
+                 trials=None, n_surrogates=0, window=0):
+        self._keep = []
+        ws = np.ascontiguousarray(window_start, np.int32)
+        self.n_points = int(ws.shape[0])
+        self.n_pairs = int(n_pairs)
+        self.n_surrogates = int(n_surrogates)
+        p = Problem()
+        p.n_pairs, p.n_trials, p.n_samples = n_pairs, n_trials, n_samples
+        p.d_y, p.d_x, p.tau, p.u, p.k = d_y, d_x, tau, u, k
+        p.n_points = self.n_points
+        p.window = int(window)
+        p.n_surrogates = int(n_surrogates)
+        I32P = ctypes.POINTER(ctypes.c_int32)
+        p.window_start = ws.ctypes.data_as(I32P)
+        self._keep.append(ws)
+        if window_len is not None:
+            wl = np.ascontiguousarray(window_len, np.int32)
+            p.window_len = wl.ctypes.data_as(I32P)
+            self._keep.append(wl)
+        if trials is not None:
+            tr = np.ascontiguousarray(trials, np.int32)
+            p.trials = tr.ctypes.data_as(I32P)
+            self._keep.append(tr)
+        h = ctypes.c_void_p()
+        check(lib().te_plan_create(ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+        self._ws = None
+        self.shape = dict(n_trials=n_trials, n_samples=n_samples)
+
+    @classmethod
+    def from_workload(cls, wl, n_surrogates=None):
+        return cls(wl.n_pairs, wl.n_trials, wl.n_samples, wl.d_y, wl.d_x, wl.tau, wl.u, wl.k, wl.window_start,
+                   wl.window_len, wl.trials, wl.n_surrogates if n_surrogates is None else n_surrogates)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().te_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self):
+        f, m, p = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        check(lib().te_plan_workspace_bytes(self._h, ctypes.byref(f), ctypes.byref(m), ctypes.byref(p)))
+        return f.value, m.value, p.value
+
+    def workspace(self, nbytes=None):
+        """A device workspace tensor (uint8) of nbytes (default: the full batched size)."""
+        torch = _torch()
+        if nbytes is None:
+            nbytes = max(self.workspace_bytes()[0], self.workspace_bytes()[2])
+        return torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+
+    def _ws_args(self, ws):
+        torch = _torch()
+        if ws is None:
+            if self._ws is None:
+                self._ws = self.workspace()
+            ws = self._ws
+        return _dev_ptr(ws, torch.uint8, "ws"), ws.numel()
+
+    def _check_series(self, x, y):
+        want = self.n_pairs * self.shape["n_trials"] * self.shape["n_samples"]
+        for name, t in (("x", x), ("y", y)):
+            if t.numel() != want:
+                raise ValueError("%s must hold n_pairs*n_trials*n_samples = %d values, got %d"
+                                 % (name, want, t.numel()))
+
+    def estimate(self, x, y, ws=None, stream=None):
+        """Plain per-window path: float64 [n_pairs, n_points] original estimates."""
+        torch = _torch()
+        self._check_series(x, y)
+        out = np.empty((self.n_pairs, self.n_points), np.float64)
+        wsp, wsn = self._ws_args(ws)
+        sh, _ = _stream_handle(stream)
+        check(lib().te_estimate(self._h, _dev_ptr(x, torch.float32, "x"), _dev_ptr(y, torch.float32, "y"), wsp, wsn,
+                                sh, _dp(out)))
+        return out
+
+    def surrogates(self, x, y, perms=None, ws=None, stream=None, use_graph=False):
+        """Batched path: (te_orig [P, C], te_surr [P, C, S], p_value [P, C])."""
+        torch = _torch()
+        self._check_series(x, y)
+        S = self.n_surrogates
+        if S > 0:
+            want = self.n_pairs * self.n_points * S * self.shape["n_trials"]
+            if perms is None or perms.numel() != want:
+                raise ValueError("perms must be int32 [n_pairs, n_points, S, n_trials] (%d values)" % want)
+        te_orig = np.empty((self.n_pairs, self.n_points), np.float64)
+        te_surr = np.empty((self.n_pairs, self.n_points, S), np.float64)
+        pv = np.empty((self.n_pairs, self.n_points), np.float64)
+        wsp, wsn = self._ws_args(ws)
+        sh, _ = _stream_handle(stream)
+        pp = ctypes.c_void_p(0) if perms is None else _dev_ptr(perms, torch.int32, "perms")
+        check(lib().te_surrogates(self._h, _dev_ptr(x, torch.float32, "x"), _dev_ptr(y, torch.float32, "y"), pp,
+                                  wsp, wsn, sh, int(bool(use_graph)), _dp(te_orig),
+                                  _dp(te_surr) if S > 0 else None, _dp(pv)))
+        return te_orig, te_surr, pv
+
+
+def knn_counts(pts, offsets, d_y, d_x, k, stream=None, ws=None, want_te=True):
+    """Neighbour statistics of pre-embedded chunks (te_knn_counts).
+
+    pts: CUDA float32 [D, stride] coordinate-major; offsets: host int64 [C+1].
+    Returns (eps float32 CUDA [total], counts int32 CUDA [3, total], te float64 [C] or None).
+    """
+    torch = _torch()
+    off = np.ascontiguousarray(offsets, np.int64)
+    C = off.shape[0] - 1
+    total = int(off[-1])
+    D = 1 + d_y + d_x
+    if pts.dim() != 2 or pts.shape[0] != D:
+        raise ValueError("pts must be [1 + d_y + d_x, stride]")
+    eps = torch.empty(max(total, 1), dtype=torch.float32, device=pts.device)
+    cnt = torch.empty((3, max(total, 1)), dtype=torch.int32, device=pts.device)
+    need = lib().te_knn_counts_workspace_bytes(C, total)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=pts.device)
+    te = np.empty(C, np.float64) if want_te else None
+    sh, _ = _stream_handle(stream)
+    check(lib().te_knn_counts(_dev_ptr(pts, torch.float32, "pts"), pts.shape[1],
+                              off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), C, d_y, d_x, k,
+                              _dev_ptr(ws, torch.uint8, "ws"), ws.numel(), sh, ctypes.c_void_p(eps.data_ptr()),
+                              ctypes.c_void_p(cnt.data_ptr()), _dp(te) if want_te else None))
+    return eps[:total], cnt[:, :total], te
+
+
+def version() -> str:
+    return lib().te_version().decode()

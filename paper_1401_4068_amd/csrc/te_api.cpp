@@ -1,0 +1,488 @@
+// te_api.cpp -- host runtime and C interface of libte.
+//
+// A plan fixes the geometry of one analysis job (Wollstadt et al. 2014:
+// eq. 10 windows, embedding of eq. 6-7, S surrogates per window).  A batch is
+// a set of chunks (search spaces) laid out in the caller's device workspace:
+//   coordinates | chunk table | item starts | embed tasks | permutation rows |
+//   per-item partial sums | per-chunk results | p-values | counters
+// The tables are built on the host, uploaded with one copy, and consumed by
+// the embed, search, reduce and p-value kernels on the caller's stream.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "te.h"
+#include "te_internal.h"
+#include "te_runtime.h"
+
+namespace te {
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_last_error;
+
+te_status fail(te_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+te_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(TE_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void clear_error() { g_last_error.clear(); }
+
+// ------------------------------------------------------------------ device
+
+static std::mutex g_dev_mu;
+static std::vector<DeviceInfo> g_devs;
+
+te_status current_device(DeviceInfo *out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    for (auto &d : g_devs)
+        if (d.device == dev) {
+            *out = d;
+            return TE_OK;
+        }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDeviceProperties");
+    DeviceInfo d;
+    d.device = dev;
+    d.n_cu = prop.multiProcessorCount;
+    std::snprintf(d.arch, sizeof d.arch, "%s", prop.gcnArchName);
+    g_devs.push_back(d);
+    *out = d;
+    return TE_OK;
+}
+
+// ------------------------------------------------------------ batch layout
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+void Batch::finish_layout()
+{
+    // LPT order: biggest chunks first so the persistent waves end together.
+    order.resize(chunks.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return chunks[a].n > chunks[b].n; });
+    std::vector<ChunkDesc> sorted;
+    sorted.reserve(chunks.size());
+    item_start.clear();
+    n_items = 0;
+    for (int c : order) {
+        ChunkDesc d = chunks[c];
+        d.item0 = (int32_t)n_items;
+        n_items += (d.n + kWave - 1) / kWave;
+        item_start.push_back(d.item0);
+        sorted.push_back(d);
+    }
+    chunks.swap(sorted);
+
+    size_t o = 0;
+    off_coords = o;
+    o = align_up(o + sizeof(float) * (size_t)n_floats, 256);
+    off_tables = o;
+    off_chunks = o;
+    o = align_up(o + sizeof(ChunkDesc) * chunks.size(), 16);
+    off_items = o;
+    o = align_up(o + sizeof(int32_t) * item_start.size(), 16);
+    off_tasks = o;
+    o = align_up(o + sizeof(EmbedTask) * tasks.size(), 16);
+    off_prow = o;
+    o = align_up(o + sizeof(int64_t) * perm_rows.size(), 16);
+    off_prc = o;
+    o = align_up(o + sizeof(int32_t) * perm_rc.size(), 16);
+    tables_bytes = o - off_tables;
+    off_partial = align_up(o, 256);
+    o = off_partial + sizeof(double) * (size_t)std::max<int64_t>(n_items, 1);
+    off_results = align_up(o, 256);
+    o = off_results + sizeof(double) * (size_t)std::max(n_results, 1);
+    off_pv = align_up(o, 256);
+    o = off_pv + sizeof(double) * (size_t)std::max(n_groups, 1);
+    off_ctr = align_up(o, 256);
+    o = off_ctr + sizeof(int32_t) * 4;
+    total_bytes = align_up(o, 256);
+
+    host_tables.assign(tables_bytes, 0);
+    std::memcpy(host_tables.data() + (off_chunks - off_tables), chunks.data(), sizeof(ChunkDesc) * chunks.size());
+    std::memcpy(host_tables.data() + (off_items - off_tables), item_start.data(),
+                sizeof(int32_t) * item_start.size());
+    if (!tasks.empty())
+        std::memcpy(host_tables.data() + (off_tasks - off_tables), tasks.data(), sizeof(EmbedTask) * tasks.size());
+    if (!perm_rows.empty()) {
+        std::memcpy(host_tables.data() + (off_prow - off_tables), perm_rows.data(),
+                    sizeof(int64_t) * perm_rows.size());
+        std::memcpy(host_tables.data() + (off_prc - off_tables), perm_rc.data(), sizeof(int32_t) * perm_rc.size());
+    }
+}
+
+// ------------------------------------------------------------------- plan
+
+static int history(const te_problem &p)
+{
+    return std::max(1 + (p.d_y - 1) * p.tau, p.u + (p.d_x - 1) * p.tau);
+}
+
+te_status Plan::build_group_batch(const std::vector<int> &groups, int n_surr, Batch *b) const
+{
+    // groups: indices g = pair * n_points + point; every group gets S+1 chunks
+    // that share one (y_t', Y_past) block.
+    b->n_groups = (int)groups.size();
+    b->n_surr = n_surr;
+    b->n_results = b->n_groups * (n_surr + 1);
+    b->groups = groups;
+    int64_t fl = 0;
+    const int dT = 1 + p.d_y, dS = p.d_x;
+    for (int gi = 0; gi < (int)groups.size(); ++gi) {
+        const int g = groups[gi];
+        const int pair = g / p.n_points, c = g % p.n_points;
+        const int N = (int)npts[c];
+        const int64_t tp = fl;
+        fl += (int64_t)dT * N;
+        for (int s = 0; s <= n_surr; ++s) {
+            ChunkDesc d{};
+            d.tp = tp;
+            d.s = fl;
+            d.ld = N;
+            d.out = -1;
+            d.n = N;
+            d.result = gi * (n_surr + 1) + s;
+            b->chunks.push_back(d);
+            EmbedTask t{};
+            t.tp = s == 0 ? tp : -1;
+            t.s = fl;
+            t.perm = -1;
+            if (s > 0) {
+                t.perm = (((int64_t)pair * p.n_points + c) * n_surr + (s - 1)) * p.n_trials;
+                b->perm_rows.push_back(t.perm);
+                b->perm_rc.push_back(trials[c]);
+            }
+            t.pair = pair;
+            t.w = wstart[c];
+            t.W = wlen[c];
+            t.Rc = trials[c];
+            t.n = N;
+            b->tasks.push_back(t);
+            fl += (int64_t)dS * N;
+        }
+    }
+    b->n_floats = fl;
+    b->finish_layout();
+    return TE_OK;
+}
+
+// Pinned host staging buffers, reused across calls.
+void *PinnedPool::take(size_t bytes)
+{
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto &b : bufs)
+        if (!b.busy && b.bytes >= bytes) {
+            b.busy = true;
+            return b.ptr;
+        }
+    Buf nb;
+    nb.bytes = std::max<size_t>(bytes, 4096);
+    if (hipHostMalloc(&nb.ptr, nb.bytes, hipHostMallocDefault) != hipSuccess)
+        return nullptr;
+    nb.busy = true;
+    bufs.push_back(nb);
+    return nb.ptr;
+}
+
+void PinnedPool::give(void *ptr)
+{
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto &b : bufs)
+        if (b.ptr == ptr)
+            b.busy = false;
+}
+
+PinnedPool::~PinnedPool()
+{
+    for (auto &b : bufs)
+        if (b.ptr)
+            hipHostFree(b.ptr);
+}
+
+Plan::~Plan()
+{
+    for (auto &g : graphs) {
+        if (g.exec)
+            hipGraphExecDestroy(g.exec);
+        if (g.graph)
+            hipGraphDestroy(g.graph);
+    }
+}
+
+// Device and launch configuration, resolved on first execution (plans can be
+// created and sized without a GPU).
+te_status Plan::ensure_device() const
+{
+    std::lock_guard<std::mutex> lk(dev_mu);
+    if (dev_ready)
+        return TE_OK;
+    te_status st = current_device(&dev);
+    if (st != TE_OK)
+        return st;
+    cfg = default_config(dev, p.d_y, p.d_x, p.k);
+    dev_ready = true;
+    return TE_OK;
+}
+
+// Grid (in waves) for a persistent search over n_items items.
+int Plan::grid_waves(int64_t n_items) const
+{
+    const int64_t full = (int64_t)dev.n_cu * cfg.wg_per_cu * cfg.waves_per_wg;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(full, n_items));
+}
+
+// Enqueue one batch: upload tables, embed, search, reduce, p-values, copy results
+// into the pinned staging block `stage` (results, p-values, error word).
+te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, const int32_t *perms, char *ws,
+                              void *stage, hipStream_t st) const
+{
+    hipError_t e;
+    char *tables_host = static_cast<char *>(stage);
+    std::memcpy(tables_host, b.host_tables.data(), b.tables_bytes);
+    e = hipMemcpyAsync(ws + b.off_tables, tables_host, b.tables_bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "upload tables");
+    int32_t *ctr = reinterpret_cast<int32_t *>(ws + b.off_ctr);
+    if ((e = launch_fill_i32(ctr, 0, 4, st)) != hipSuccess)
+        return hip_fail(e, "fill");
+    float *base = reinterpret_cast<float *>(ws + b.off_coords);
+    if (!b.perm_rows.empty()) {
+        e = launch_check_perms(perms, reinterpret_cast<const int64_t *>(ws + b.off_prow),
+                               reinterpret_cast<const int32_t *>(ws + b.off_prc), (int)b.perm_rows.size(), ctr + 1,
+                               st);
+        if (e != hipSuccess)
+            return hip_fail(e, "check_perms launch");
+    }
+    e = launch_embed(x, y, perms, reinterpret_cast<const EmbedTask *>(ws + b.off_tasks), (int)b.tasks.size(), base,
+                     p.n_trials, p.n_samples, p.d_y, p.d_x, p.tau, p.u, ctr + 1, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "embed launch");
+    SearchArgs a{};
+    a.base = base;
+    a.chunks = reinterpret_cast<const ChunkDesc *>(ws + b.off_chunks);
+    a.item_start = reinterpret_cast<const int32_t *>(ws + b.off_items);
+    a.n_chunks = (int32_t)b.chunks.size();
+    a.n_items = (int32_t)b.n_items;
+    a.k = p.k;
+    a.counter = ctr;
+    a.partial = reinterpret_cast<double *>(ws + b.off_partial);
+    a.eps_out = nullptr;
+    a.cnt_out = nullptr;
+    a.cnt_stride = 0;
+    if ((e = launch_search(a, p.d_y, p.d_x, cfg, grid_waves(b.n_items), st)) != hipSuccess)
+        return hip_fail(e, "search launch");
+    double *res = reinterpret_cast<double *>(ws + b.off_results);
+    if ((e = launch_reduce(a.chunks, a.n_chunks, a.partial, p.k, ctr + 1, res, st)) != hipSuccess)
+        return hip_fail(e, "reduce launch");
+    double *pv = reinterpret_cast<double *>(ws + b.off_pv);
+    if ((e = launch_pvalues(res, b.n_groups, b.n_surr, pv, st)) != hipSuccess)
+        return hip_fail(e, "pvalue launch");
+    char *out = tables_host + align_up(b.tables_bytes, 256);
+    e = hipMemcpyAsync(out, res, sizeof(double) * b.n_results, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out + sizeof(double) * b.n_results, pv, sizeof(double) * b.n_groups,
+                           hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out + sizeof(double) * (b.n_results + b.n_groups), ctr + 1, sizeof(int32_t),
+                           hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "download results");
+    return TE_OK;
+}
+
+size_t Batch::stage_bytes() const
+{
+    return align_up(tables_bytes, 256) + sizeof(double) * (n_results + n_groups) + 64;
+}
+
+te_status Plan::unpack_batch(const Batch &b, const void *stage, double *te_orig, double *te_surr, double *p_value,
+                             bool *bad_input) const
+{
+    const char *out = static_cast<const char *>(stage) + align_up(b.tables_bytes, 256);
+    const double *res = reinterpret_cast<const double *>(out);
+    const double *pv = res + b.n_results;
+    int32_t err = 0;
+    std::memcpy(&err, out + sizeof(double) * (b.n_results + b.n_groups), sizeof err);
+    for (int gi = 0; gi < b.n_groups; ++gi) {
+        const int g = b.groups[gi];
+        const double *r = res + (size_t)gi * (b.n_surr + 1);
+        if (te_orig)
+            te_orig[g] = r[0];
+        if (te_surr)
+            for (int s = 0; s < b.n_surr; ++s)
+                te_surr[(size_t)g * b.n_surr + s] = r[1 + s];
+        if (p_value)
+            p_value[g] = pv[gi];
+    }
+    if (err)
+        *bad_input = true;
+    return TE_OK;
+}
+
+}  // namespace te
+
+using namespace te;
+
+// =================================================================== C ABI
+
+extern "C" {
+
+const char *te_version(void) { return "libte 0.1 (gfx950)"; }
+
+const char *te_last_error(void) { return g_last_error.c_str(); }
+
+te_status te_plan_create(const te_problem *pr, te_plan *out)
+{
+    clear_error();
+    if (!pr || !out)
+        return fail(TE_ERR_INVALID, "null argument");
+    *out = nullptr;
+    const te_problem &p = *pr;
+    if (p.n_pairs < 1 || p.n_trials < 1 || p.n_samples < 1 || p.n_points < 1)
+        return fail(TE_ERR_INVALID, "n_pairs, n_trials, n_samples and n_points must be >= 1");
+    if (p.d_y < 1 || p.d_y > kMaxDimY || p.d_x < 1 || p.d_x > kMaxDimX)
+        return fail(TE_ERR_INVALID, "d_y and d_x must be in 1..4 (got %d, %d)", p.d_y, p.d_x);
+    if (p.tau < 1 || p.u < 1)
+        return fail(TE_ERR_INVALID, "tau and u must be >= 1");
+    if (p.k < 1 || p.k > kMaxK)
+        return fail(TE_ERR_INVALID, "k must be in 1..%d", kMaxK);
+    if (p.n_surrogates < 0)
+        return fail(TE_ERR_INVALID, "n_surrogates must be >= 0");
+    if (!p.window_start)
+        return fail(TE_ERR_INVALID, "window_start is required");
+    auto plan = std::make_unique<te_plan_s>();
+    Plan &P = plan->impl;
+    P.p = p;
+    const int h = history(p);
+    for (int c = 0; c < p.n_points; ++c) {
+        const int w = p.window_start[c];
+        const int W = p.window_len ? p.window_len[c] : p.window;
+        const int Rc = p.trials ? p.trials[c] : p.n_trials;
+        if (W < 1)
+            return fail(TE_ERR_INVALID, "window %d: length %d < 1", c, W);
+        if (w < h)
+            return fail(TE_ERR_INVALID, "window %d starts at %d but the embedding needs %d samples of history", c,
+                        w, h);
+        if ((int64_t)w + W > p.n_samples)
+            return fail(TE_ERR_INVALID, "window %d [%d, %d) runs past n_samples = %d", c, w, w + W, p.n_samples);
+        if (Rc < 1 || Rc > p.n_trials)
+            return fail(TE_ERR_INVALID, "window %d: trials %d outside 1..%d", c, Rc, p.n_trials);
+        const int64_t N = (int64_t)Rc * W;
+        if (N <= p.k)
+            return fail(TE_ERR_INVALID, "window %d pools %lld points, need more than k = %d", c, (long long)N, p.k);
+        if (N > (1 << 30))
+            return fail(TE_ERR_INVALID, "window %d pools too many points", c);
+        P.wstart.push_back(w);
+        P.wlen.push_back(W);
+        P.trials.push_back(Rc);
+        P.npts.push_back(N);
+    }
+    P.p.window_start = nullptr;
+    P.p.window_len = nullptr;
+    P.p.trials = nullptr;
+    if (!search_supported(p.d_y, p.d_x, p.k, 8))
+        return fail(TE_ERR_INVALID, "no search kernel for d_y=%d d_x=%d k=%d", p.d_y, p.d_x, p.k);
+    // full batch: every (pair, point) with all surrogates
+    std::vector<int> all(p.n_pairs * p.n_points);
+    std::iota(all.begin(), all.end(), 0);
+    P.build_group_batch(all, p.n_surrogates, &P.full);
+    // largest single group bounds the minimum workspace
+    size_t mn = 0;
+    for (int c = 0; c < p.n_points; ++c) {
+        Batch one;
+        P.build_group_batch({c}, p.n_surrogates, &one);
+        mn = std::max(mn, one.total_bytes);
+    }
+    P.min_bytes = mn;
+    // plain path: one window at a time, originals only
+    int64_t maxn = *std::max_element(P.npts.begin(), P.npts.end());
+    P.plain_bytes = align_up(sizeof(float) * (size_t)maxn * (1 + p.d_y + p.d_x), 256) +
+                    align_up(sizeof(double) * (size_t)((maxn + kWave - 1) / kWave), 256) +
+                    align_up(sizeof(double) * (size_t)p.n_pairs * p.n_points, 256) +
+                    align_up(sizeof(int32_t) * 4 * (size_t)p.n_pairs * p.n_points + 16, 256) +
+                    align_up((sizeof(ChunkDesc) + sizeof(EmbedTask) + 16) * (size_t)p.n_pairs * p.n_points, 256) +
+                    4096;
+    *out = plan.release();
+    return TE_OK;
+}
+
+te_status te_plan_destroy(te_plan plan)
+{
+    delete plan;
+    return TE_OK;
+}
+
+te_status te_plan_workspace_bytes(te_plan plan, size_t *full, size_t *minimum, size_t *plain)
+{
+    clear_error();
+    if (!plan)
+        return fail(TE_ERR_INVALID, "null plan");
+    if (full)
+        *full = plan->impl.full.total_bytes;
+    if (minimum)
+        *minimum = plan->impl.min_bytes;
+    if (plain)
+        *plain = plan->impl.plain_bytes;
+    return TE_OK;
+}
+
+te_status te_estimate(te_plan plan, const float *x, const float *y, void *ws, size_t ws_bytes, void *hip_stream,
+                      double *te_out)
+{
+    clear_error();
+    if (!plan || !x || !y || !ws || !te_out)
+        return fail(TE_ERR_INVALID, "null argument");
+    te_status s = plan->impl.ensure_device();
+    if (s != TE_OK)
+        return s;
+    return plan->impl.estimate_plain(x, y, static_cast<char *>(ws), ws_bytes, (hipStream_t)hip_stream, te_out);
+}
+
+te_status te_surrogates(te_plan plan, const float *x, const float *y, const int32_t *perms, void *ws,
+                        size_t ws_bytes, void *hip_stream, int32_t use_graph, double *te_orig, double *te_surr,
+                        double *p_value)
+{
+    clear_error();
+    if (!plan || !x || !y || !ws || !te_orig)
+        return fail(TE_ERR_INVALID, "null argument");
+    const Plan &P = plan->impl;
+    if (P.p.n_surrogates > 0 && (!perms || !te_surr))
+        return fail(TE_ERR_INVALID, "n_surrogates > 0 needs perms and te_surr");
+    te_status s = plan->impl.ensure_device();
+    if (s != TE_OK)
+        return s;
+    return plan->impl.run_surrogates(x, y, perms, static_cast<char *>(ws), ws_bytes, (hipStream_t)hip_stream,
+                                     use_graph != 0, te_orig, te_surr, p_value);
+}
+
+}  // extern "C"

@@ -1,0 +1,401 @@
+// te_exec.cpp -- execution paths of libte: the batched surrogate path (one
+// persistent search launch per batch, optional hipGraph replay), the plain
+// per-window path, and the pre-embedded neighbour-count export.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "te.h"
+#include "te_internal.h"
+#include "te_runtime.h"
+
+namespace te {
+
+int search_occupancy(int d_y, int d_x, int k, int slots, int waves_per_wg);
+
+SearchConfig default_config(const DeviceInfo &dev, int d_y, int d_x, int k)
+{
+    (void)dev;
+    SearchConfig c;
+    c.slots = 8;
+    c.waves_per_wg = 4;
+    const int occ = search_occupancy(d_y, d_x, k, c.slots, c.waves_per_wg);
+    c.wg_per_cu = std::max(1, occ);
+    return c;
+}
+
+// Split the full batch into batches whose layout fits ws_bytes; groups (all S+1
+// chunks of one (pair, point)) are never split.  Results do not depend on the split.
+te_status Plan::split_batches(size_t ws_bytes, std::vector<Batch> *out) const
+{
+    const int G = p.n_pairs * p.n_points;
+    std::vector<int> cur;
+    for (int g = 0; g < G; ++g) {
+        std::vector<int> trial = cur;
+        trial.push_back(g);
+        Batch b;
+        build_group_batch(trial, p.n_surrogates, &b);
+        if (b.total_bytes <= ws_bytes) {
+            cur.swap(trial);
+            continue;
+        }
+        if (cur.empty())
+            return fail(TE_ERR_NOMEM, "workspace of %zu bytes cannot hold window group %d (%zu bytes)", ws_bytes, g,
+                        b.total_bytes);
+        out->emplace_back();
+        build_group_batch(cur, p.n_surrogates, &out->back());
+        cur.assign(1, g);
+    }
+    if (!cur.empty()) {
+        out->emplace_back();
+        build_group_batch(cur, p.n_surrogates, &out->back());
+    }
+    return TE_OK;
+}
+
+te_status Plan::run_surrogates(const float *x, const float *y, const int32_t *perms, char *ws, size_t ws_bytes,
+                               hipStream_t st, bool use_graph, double *te_orig, double *te_surr,
+                               double *p_value) const
+{
+    if (ws_bytes < min_bytes)
+        return fail(TE_ERR_NOMEM, "workspace %zu bytes < minimum %zu", ws_bytes, min_bytes);
+    hipError_t e;
+
+    if (use_graph) {
+        std::lock_guard<std::mutex> lk(graph_mu);
+        GraphEntry *ge = nullptr;
+        for (auto &g : graphs)
+            if (g.x == x && g.y == y && g.perms == perms && g.ws == ws && g.stream == st && g.ws_bytes == ws_bytes)
+                ge = &g;
+        if (!ge) {
+            GraphEntry ne;
+            ne.x = x;
+            ne.y = y;
+            ne.perms = perms;
+            ne.ws = ws;
+            ne.stream = st;
+            ne.ws_bytes = ws_bytes;
+            if (ws_bytes >= full.total_bytes) {
+                ne.batches.push_back(full);
+            } else {
+                te_status s2 = split_batches(ws_bytes, &ne.batches);
+                if (s2 != TE_OK)
+                    return s2;
+            }
+            for (auto &b : ne.batches) {
+                void *stg = pool.take(b.stage_bytes());
+                if (!stg)
+                    return fail(TE_ERR_NOMEM, "pinned staging allocation failed");
+                ne.stages.push_back(stg);
+            }
+            if (st == nullptr)
+                return fail(TE_ERR_INVALID, "graph capture needs a non-default stream");
+            e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess)
+                return hip_fail(e, "hipStreamBeginCapture");
+            te_status s2 = TE_OK;
+            for (size_t i = 0; i < ne.batches.size() && s2 == TE_OK; ++i)
+                s2 = enqueue_batch(ne.batches[i], x, y, perms, ws, ne.stages[i], st);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(st, &graph);
+            if (s2 != TE_OK) {
+                if (graph)
+                    hipGraphDestroy(graph);
+                return s2;
+            }
+            if (e != hipSuccess)
+                return hip_fail(e, "hipStreamEndCapture");
+            hipGraphExec_t exec = nullptr;
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                hipGraphDestroy(graph);
+                return hip_fail(e, "hipGraphInstantiate");
+            }
+            ne.graph = graph;
+            ne.exec = exec;
+            graphs.push_back(std::move(ne));
+            ge = &graphs.back();
+        }
+        if ((e = hipGraphLaunch(ge->exec, st)) != hipSuccess)
+            return hip_fail(e, "hipGraphLaunch");
+        if ((e = hipStreamSynchronize(st)) != hipSuccess)
+            return hip_fail(e, "hipStreamSynchronize");
+        bool bad = false;
+        for (size_t i = 0; i < ge->batches.size(); ++i)
+            unpack_batch(ge->batches[i], ge->stages[i], te_orig, te_surr, p_value, &bad);
+        if (bad)
+            return fail(TE_ERR_INVALID, "non-finite input value or invalid surrogate permutation");
+        return TE_OK;
+    }
+
+    std::vector<Batch> local;
+    const std::vector<Batch> *batches = &local;
+    std::vector<Batch> one;
+    if (ws_bytes >= full.total_bytes) {
+        one.push_back(full);
+        batches = &one;
+    } else {
+        te_status s2 = split_batches(ws_bytes, &local);
+        if (s2 != TE_OK)
+            return s2;
+    }
+    std::vector<void *> stages;
+    te_status s = TE_OK;
+    for (const Batch &b : *batches) {
+        void *stg = pool.take(b.stage_bytes());
+        if (!stg) {
+            s = fail(TE_ERR_NOMEM, "pinned staging allocation failed");
+            break;
+        }
+        stages.push_back(stg);
+        s = enqueue_batch(b, x, y, perms, ws, stg, st);
+        if (s != TE_OK)
+            break;
+    }
+    if (s == TE_OK && (e = hipStreamSynchronize(st)) != hipSuccess)
+        s = hip_fail(e, "hipStreamSynchronize");
+    bool bad = false;
+    if (s == TE_OK)
+        for (size_t i = 0; i < batches->size(); ++i)
+            unpack_batch((*batches)[i], stages[i], te_orig, te_surr, p_value, &bad);
+    for (void *stg : stages)
+        pool.give(stg);
+    if (s == TE_OK && bad)
+        s = fail(TE_ERR_INVALID, "non-finite input value or invalid surrogate permutation");
+    return s;
+}
+
+// Plain path: each (pair, window) on its own -- embed, search, reduce -- in
+// window order on one stream; all estimates are copied back at the end.
+te_status Plan::estimate_plain(const float *x, const float *y, char *ws, size_t ws_bytes, hipStream_t st,
+                               double *te_out) const
+{
+    if (ws_bytes < plain_bytes)
+        return fail(TE_ERR_NOMEM, "workspace %zu bytes < plain-path size %zu", ws_bytes, plain_bytes);
+    const int G = p.n_pairs * p.n_points;
+    const int D = 1 + p.d_y + p.d_x;
+    const int64_t maxn = *std::max_element(npts.begin(), npts.end());
+    size_t o = 0;
+    const size_t off_coords = o;
+    o = align_up(o + sizeof(float) * (size_t)maxn * D, 256);
+    const size_t off_partial = o;
+    o = align_up(o + sizeof(double) * (size_t)((maxn + kWave - 1) / kWave), 256);
+    const size_t off_results = o;
+    o = align_up(o + sizeof(double) * (size_t)G, 256);
+    const size_t off_ctr = o;
+    o = align_up(o + sizeof(int32_t) * 4 * (size_t)G + 16, 256);
+    const size_t off_tables = o;
+    const size_t tbl_chunks = 0;
+    const size_t tbl_items = align_up(sizeof(ChunkDesc) * G, 16);
+    const size_t tbl_tasks = tbl_items + align_up(sizeof(int32_t) * G, 16);
+    const size_t tbl_bytes = tbl_tasks + sizeof(EmbedTask) * G;
+
+    const size_t out_off = align_up(tbl_bytes, 256);
+    char *stg = static_cast<char *>(pool.take(out_off + sizeof(double) * G + sizeof(int32_t) * 4 * G));
+    if (!stg)
+        return fail(TE_ERR_NOMEM, "pinned staging allocation failed");
+    ChunkDesc *hc = reinterpret_cast<ChunkDesc *>(stg + tbl_chunks);
+    int32_t *hi = reinterpret_cast<int32_t *>(stg + tbl_items);
+    EmbedTask *ht = reinterpret_cast<EmbedTask *>(stg + tbl_tasks);
+    const int dT = 1 + p.d_y;
+    for (int g = 0; g < G; ++g) {
+        const int pair = g / p.n_points, c = g % p.n_points;
+        const int N = (int)npts[c];
+        ChunkDesc d{};
+        d.tp = 0;
+        d.s = (int64_t)dT * N;
+        d.ld = N;
+        d.out = -1;
+        d.n = N;
+        d.item0 = 0;
+        d.result = g;
+        hc[g] = d;
+        hi[g] = 0;
+        EmbedTask t{};
+        t.tp = 0;
+        t.s = (int64_t)dT * N;
+        t.perm = -1;
+        t.pair = pair;
+        t.w = wstart[c];
+        t.W = wlen[c];
+        t.Rc = trials[c];
+        t.n = N;
+        ht[g] = t;
+    }
+    hipError_t e = hipMemcpyAsync(ws + off_tables, stg, tbl_bytes, hipMemcpyHostToDevice, st);
+    int32_t *ctr = reinterpret_cast<int32_t *>(ws + off_ctr);
+    if (e == hipSuccess)
+        e = launch_fill_i32(ctr, 0, 4 * (int64_t)G, st);
+    float *base = reinterpret_cast<float *>(ws + off_coords);
+    double *partial = reinterpret_cast<double *>(ws + off_partial);
+    double *res = reinterpret_cast<double *>(ws + off_results);
+    const ChunkDesc *dc = reinterpret_cast<const ChunkDesc *>(ws + off_tables + tbl_chunks);
+    const int32_t *di = reinterpret_cast<const int32_t *>(ws + off_tables + tbl_items);
+    const EmbedTask *dt = reinterpret_cast<const EmbedTask *>(ws + off_tables + tbl_tasks);
+    for (int g = 0; g < G && e == hipSuccess; ++g) {
+        const int c = g % p.n_points;
+        const int64_t items = (npts[c] + kWave - 1) / kWave;
+        e = launch_embed(x, y, nullptr, dt + g, 1, base, p.n_trials, p.n_samples, p.d_y, p.d_x, p.tau, p.u,
+                         ctr + 4 * g + 1, st);
+        if (e != hipSuccess)
+            break;
+        SearchArgs a{};
+        a.base = base;
+        a.chunks = dc + g;
+        a.item_start = di + g;
+        a.n_chunks = 1;
+        a.n_items = (int32_t)items;
+        a.k = p.k;
+        a.counter = ctr + 4 * g;
+        a.partial = partial;
+        e = launch_search(a, p.d_y, p.d_x, cfg, grid_waves(items), st);
+        if (e != hipSuccess)
+            break;
+        e = launch_reduce(dc + g, 1, partial, p.k, ctr + 4 * g + 1, res, st);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(stg + out_off, res, sizeof(double) * G, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(stg + out_off + sizeof(double) * G, ctr, sizeof(int32_t) * 4 * G, hipMemcpyDeviceToHost,
+                           st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        pool.give(stg);
+        return hip_fail(e, "plain path");
+    }
+    std::memcpy(te_out, stg + out_off, sizeof(double) * G);
+    const int32_t *errs = reinterpret_cast<const int32_t *>(stg + out_off + sizeof(double) * G);
+    bool bad = false;
+    for (int g = 0; g < G; ++g)
+        bad |= errs[4 * g + 1] != 0;
+    pool.give(stg);
+    if (bad)
+        return fail(TE_ERR_INVALID, "non-finite input value");
+    return TE_OK;
+}
+
+static PinnedPool g_knn_pool;
+
+}  // namespace te
+
+using namespace te;
+
+extern "C" {
+
+size_t te_knn_counts_workspace_bytes(int32_t n_chunks, int64_t n_points_total)
+{
+    if (n_chunks < 1 || n_points_total < 0)
+        return 0;
+    const size_t items = (size_t)(n_points_total / kWave + n_chunks + 1);
+    return align_up(sizeof(ChunkDesc) * n_chunks, 256) + align_up(sizeof(int32_t) * n_chunks, 256) +
+           align_up(sizeof(double) * items, 256) + align_up(sizeof(double) * n_chunks, 256) + 256 + 256;
+}
+
+te_status te_knn_counts(const float *pts, int64_t dim_stride, const int64_t *offsets, int32_t n_chunks, int32_t d_y,
+                        int32_t d_x, int32_t k, void *ws_, size_t ws_bytes, void *hip_stream, float *eps,
+                        int32_t *counts, double *te_out)
+{
+    clear_error();
+    if (!pts || !offsets || !ws_ || !eps || !counts)
+        return fail(TE_ERR_INVALID, "null argument");
+    if (n_chunks < 1)
+        return fail(TE_ERR_INVALID, "n_chunks must be >= 1");
+    if (d_y < 1 || d_y > kMaxDimY || d_x < 1 || d_x > kMaxDimX || k < 1 || k > kMaxK)
+        return fail(TE_ERR_INVALID, "unsupported d_y=%d d_x=%d k=%d", d_y, d_x, k);
+    const int64_t total = offsets[n_chunks];
+    if (offsets[0] != 0 || total > dim_stride)
+        return fail(TE_ERR_INVALID, "offsets must start at 0 and end at or below dim_stride");
+    int64_t items = 0;
+    std::vector<ChunkDesc> chunks(n_chunks);
+    for (int c = 0; c < n_chunks; ++c) {
+        const int64_t n = offsets[c + 1] - offsets[c];
+        if (n <= k || n > (1 << 30))
+            return fail(TE_ERR_INVALID, "chunk %d has %lld points; need k < n <= 2^30", c, (long long)n);
+        ChunkDesc d{};
+        d.tp = offsets[c];
+        d.s = offsets[c] + (int64_t)(1 + d_y) * dim_stride;
+        d.ld = dim_stride;
+        d.out = offsets[c];
+        d.n = (int32_t)n;
+        d.result = c;
+        chunks[c] = d;
+    }
+    // longest first
+    std::vector<int> order(n_chunks);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return chunks[a].n > chunks[b].n; });
+    std::vector<ChunkDesc> sorted(n_chunks);
+    std::vector<int32_t> starts(n_chunks);
+    for (int i = 0; i < n_chunks; ++i) {
+        sorted[i] = chunks[order[i]];
+        sorted[i].item0 = (int32_t)items;
+        starts[i] = (int32_t)items;
+        items += (sorted[i].n + kWave - 1) / kWave;
+    }
+    if (ws_bytes < te_knn_counts_workspace_bytes(n_chunks, total))
+        return fail(TE_ERR_NOMEM, "workspace too small");
+    DeviceInfo dev;
+    te_status s = current_device(&dev);
+    if (s != TE_OK)
+        return s;
+    SearchConfig cfg = default_config(dev, d_y, d_x, k);
+    char *ws = static_cast<char *>(ws_);
+    size_t o = 0;
+    const size_t off_chunks = o;
+    o = align_up(o + sizeof(ChunkDesc) * n_chunks, 256);
+    const size_t off_items = o;
+    o = align_up(o + sizeof(int32_t) * n_chunks, 256);
+    const size_t off_partial = o;
+    o = align_up(o + sizeof(double) * (size_t)items, 256);
+    const size_t off_results = o;
+    o = align_up(o + sizeof(double) * n_chunks, 256);
+    const size_t off_ctr = o;
+    const size_t tbytes = off_partial;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t out_off = align_up(tbytes, 256);
+    char *stg = static_cast<char *>(g_knn_pool.take(out_off + sizeof(double) * n_chunks + 64));
+    if (!stg)
+        return fail(TE_ERR_NOMEM, "pinned staging allocation failed");
+    std::memcpy(stg + off_chunks, sorted.data(), sizeof(ChunkDesc) * n_chunks);
+    std::memcpy(stg + off_items, starts.data(), sizeof(int32_t) * n_chunks);
+    hipError_t e = hipMemcpyAsync(ws, stg, tbytes, hipMemcpyHostToDevice, st);
+    int32_t *ctr = reinterpret_cast<int32_t *>(ws + off_ctr);
+    if (e == hipSuccess)
+        e = launch_fill_i32(ctr, 0, 4, st);
+    SearchArgs a{};
+    a.base = pts;
+    a.chunks = reinterpret_cast<const ChunkDesc *>(ws + off_chunks);
+    a.item_start = reinterpret_cast<const int32_t *>(ws + off_items);
+    a.n_chunks = n_chunks;
+    a.n_items = (int32_t)items;
+    a.k = k;
+    a.counter = ctr;
+    a.partial = reinterpret_cast<double *>(ws + off_partial);
+    a.eps_out = eps;
+    a.cnt_out = counts;
+    a.cnt_stride = total;
+    if (e == hipSuccess) {
+        const int64_t full = (int64_t)dev.n_cu * cfg.wg_per_cu * cfg.waves_per_wg;
+        e = launch_search(a, d_y, d_x, cfg, (int)std::max<int64_t>(1, std::min<int64_t>(full, items)), st);
+    }
+    double *res = reinterpret_cast<double *>(ws + off_results);
+    if (e == hipSuccess)
+        e = launch_reduce(a.chunks, n_chunks, a.partial, k, ctr + 1, res, st);
+    if (e == hipSuccess && te_out)
+        e = hipMemcpyAsync(stg + out_off, res, sizeof(double) * n_chunks, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e == hipSuccess && te_out)
+        std::memcpy(te_out, stg + out_off, sizeof(double) * n_chunks);
+    g_knn_pool.give(stg);
+    if (e != hipSuccess)
+        return hip_fail(e, "te_knn_counts");
+    return TE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// te_internal.h -- structures shared by the host runtime and the HIP kernels of libte.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace te {
+
+// Largest supported embedding dimensions and neighbour count.
+constexpr int kMaxDimY = 4;
+constexpr int kMaxDimX = 4;
+constexpr int kMaxK = 15;
+constexpr int kWave = 64;                 // wavefront width on gfx950
+constexpr int kMaxWavesPerWG = 4;         // search kernel workgroup: up to 4 independent waves
+
+// One search space ("chunk", eq. 10 pooled points) as the kernels see it.
+// Coordinate m of point j lives at
+//   base[tp + m * ld + j]                 for m <  1 + d_y  (y_t' and target past)
+//   base[s + (m - 1 - d_y) * ld + j]      for m >= 1 + d_y  (source past)
+// so the originals and surrogates of one window share the (y_t', Y_past) block.
+struct ChunkDesc {
+    int64_t tp;       // float offset of the target block
+    int64_t s;        // float offset of the source block
+    int64_t ld;       // stride between coordinates, in floats
+    int64_t out;      // per-point output offset (eps / counts), or -1
+    int32_t n;        // points in the chunk
+    int32_t item0;    // index of the chunk's first work item (64 references each)
+    int32_t result;   // slot of the chunk's estimate in the result array
+    int32_t pad_;
+};
+
+// Work for the embedding kernel: writes one chunk's source block, and the
+// target block when tp >= 0.
+struct EmbedTask {
+    int64_t tp;       // float offset of the target block, or -1
+    int64_t s;        // float offset of the source block
+    int64_t perm;     // int32 offset of the source permutation row, or -1 (identity)
+    int32_t pair, w, W, Rc;
+    int32_t n;        // Rc * W
+    int32_t pad_;
+};
+
+// Arguments of the search kernel (passed by value; read from the kernarg segment).
+struct SearchArgs {
+    const float *base;          // coordinate storage
+    const ChunkDesc *chunks;    // [n_chunks] in schedule order
+    const int32_t *item_start;  // [n_chunks] chunks[c].item0, ascending
+    int32_t n_chunks;
+    int32_t n_items;
+    int32_t k;
+    int32_t pad_;
+    int32_t *counter;           // work-queue head, zero before launch
+    double *partial;            // [n_items] per-item sum of psi terms
+    float *eps_out;             // optional per-point radius
+    int32_t *cnt_out;           // optional per-point counts [3][cnt_stride]
+    int64_t cnt_stride;
+};
+
+// Tunable launch shape of the search kernel.
+struct SearchConfig {
+    int slots;        // candidate slots per lane in the counting pass (4 or 8)
+    int waves_per_wg; // independent wavefronts per workgroup
+    int wg_per_cu;    // persistent workgroups per compute unit
+};
+
+struct DeviceInfo {
+    int device = -1;
+    int n_cu = 0;
+    char arch[64] = {0};
+};
+
+// Kernel launchers (te_kernels.hip).  All return hipSuccess or the launch error.
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
+hipError_t launch_embed(const float *x, const float *y, const int32_t *perms, const EmbedTask *tasks,
+                        int n_tasks, float *base, int R, int T, int d_y, int d_x, int tau, int u,
+                        int32_t *err, hipStream_t st);
+hipError_t launch_check_perms(const int32_t *perms, const int64_t *rows, const int32_t *rc, int n_rows,
+                              int32_t *err, hipStream_t st);
+hipError_t launch_search(const SearchArgs &a, int d_y, int d_x, const SearchConfig &cfg, int grid_waves,
+                         hipStream_t st);
+hipError_t launch_reduce(const ChunkDesc *chunks, int n_chunks, const double *partial, int k,
+                         const int32_t *err, double *results, hipStream_t st);
+hipError_t launch_pvalues(const double *results, int n_groups, int n_surr, double *pv, hipStream_t st);
+bool search_supported(int d_y, int d_x, int k, int slots);
+
+}  // namespace te

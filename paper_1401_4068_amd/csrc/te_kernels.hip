@@ -1,0 +1,584 @@
+// te_kernels.hip -- HIP kernels of libte for gfx950 (CDNA4, wave64).
+//
+//   embed_kernel     eq. 6-7 / eq. 10: gathers the pooled points of a window
+//                    from the raw [pair][trial][sample] series into
+//                    coordinate-major blocks; bit copies only.
+//   search_kernel    the KSG type-1 searches (text before eq. 9): per point
+//                    the max-norm k-NN radius in the joint space, then strict
+//                    range counts in the three marginal spaces of eq. 8, then
+//                    the per-point digamma terms of eq. 9 summed per work item.
+//   reduce_kernel    eq. 9/10 per chunk: psi(k) + mean of the terms.
+//   pvalue_kernel    fraction of surrogate estimates >= the original.
+//
+// The search kernel is persistent: every wavefront pulls work items (one
+// chunk, 64 consecutive reference points) from a global counter until the
+// queue is empty, so one launch covers any mix of chunk sizes.
+//
+// Pass 1 (radius): lane = reference point.  Candidates are wave-uniform and
+// read with scalar loads straight into SGPRs, so each coordinate difference is
+// one v_sub_f32 with an SGPR operand.  Each lane keeps the k+1 smallest joint
+// distances in registers (self included, distance 0), inserted with a
+// min / med3 network only when some lane of the wave improves its k+1-th
+// distance; the radius is the k+1-th entry, i.e. the k-th neighbour without self.
+//
+// Pass 2 (counts): lane = candidate point.  Each wave holds a tile of 64 x
+// SLOTS candidates in VGPRs and walks its 64 references uniformly (scalar
+// loads), with the reference radius in an SGPR: the three strict comparisons
+// become wave ballots and the counting is SALU popcounts.  The (y_t', Y_past)
+// and (Y_past, X_past) conditions share the Y_past comparison:
+// n_TP counts  [d_P < eps] & [d_T < eps],  n_PS counts [d_P < eps] & [d_S < eps].
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "te_internal.h"
+
+namespace te {
+
+namespace {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) float cfloat_t;
+typedef const __attribute__((address_space(4))) int32_t cint_t;
+typedef const __attribute__((address_space(4))) int64_t cint64_t;
+typedef const __attribute__((address_space(4))) f4v __attribute__((aligned(4))) cf4_t;
+
+// Wave-uniform loads through the constant address space: the address is the
+// same in every lane, so these become scalar (SMEM) loads into SGPRs.  Only
+// scalar and vector-typed values are loaded this way (aggregate copies would
+// be lowered to vector-memory loads).
+__device__ __forceinline__ float uload(const float *p) { return *(cfloat_t *)p; }
+__device__ __forceinline__ f4v uload4(const float *p) { return *(cf4_t *)p; }
+__device__ __forceinline__ int32_t uload_i(const int32_t *p) { return *(cint_t *)p; }
+__device__ __forceinline__ int64_t uload_l(const int64_t *p) { return *(cint64_t *)p; }
+
+// Compiler barrier that keeps a uniform branch a branch (a block containing it
+// cannot be speculated and if-converted into selects).
+__device__ __forceinline__ void keep_branch() { asm volatile("" ::: "memory"); }
+
+constexpr float kInf = __builtin_inff();
+
+__device__ __forceinline__ float absdiff(float a, float b) { return __builtin_fabsf(a - b); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// psi(n + 1) = -gamma + H_n for integer n >= 0 in float64: upward recurrence
+// psi(x) = psi(x + 1) - 1/x to x >= 16, then the asymptotic (Stirling-type)
+// series psi(x) ~ ln x - 1/(2x) - sum_j B_2j / (2j x^2j) through B_10
+// (Abramowitz & Stegun 6.3.18); truncation error < 1e-16 at x >= 16.
+__device__ double psi_of_count(int n)
+{
+    double x = (double)n + 1.0;
+    double shift = 0.0;
+    while (x < 16.0) {
+        shift -= 1.0 / x;
+        x += 1.0;
+    }
+    const double r = 1.0 / x;
+    const double r2 = r * r;
+    const double series =
+        r2 * (1.0 / 12 - r2 * (1.0 / 120 - r2 * (1.0 / 252 - r2 * (1.0 / 240 - r2 * (1.0 / 132)))));
+    return log(x) - 0.5 * r - series + shift;
+}
+
+// Fixed-order butterfly sum over the 64 lanes (same order on every call).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Per-chunk coordinate base pointers (wave-uniform).
+template <int DY, int DX>
+struct Coords {
+    static constexpr int D = 1 + DY + DX;
+    const float *p[D];
+    __device__ __forceinline__ Coords(const float *base, const ChunkDesc &c)
+    {
+#pragma unroll
+        for (int m = 0; m < D; ++m)
+            p[m] = (m < 1 + DY) ? base + c.tp + (int64_t)m * c.ld : base + c.s + (int64_t)(m - 1 - DY) * c.ld;
+    }
+};
+
+// Joint, target-future, target-past and source-past distances of one pair.
+template <int DY, int DX>
+struct PairDist {
+    float t, p, s;
+};
+
+template <int DY, int DX>
+__device__ __forceinline__ PairDist<DY, DX> pair_dist(const float (&a)[1 + DY + DX], const float (&b)[1 + DY + DX])
+{
+    PairDist<DY, DX> d;
+    d.t = absdiff(a[0], b[0]);
+    float p = absdiff(a[1], b[1]);
+#pragma unroll
+    for (int m = 2; m < 1 + DY; ++m)
+        p = fmaxf(p, absdiff(a[m], b[m]));
+    float s = absdiff(a[1 + DY], b[1 + DY]);
+#pragma unroll
+    for (int m = 2 + DY; m < 1 + DY + DX; ++m)
+        s = fmaxf(s, absdiff(a[m], b[m]));
+    d.p = p;
+    d.s = s;
+    return d;
+}
+
+template <int DY, int DX, int RW>
+__device__ __forceinline__ PairDist<DY, DX> pair_dist_row(const float (&a)[RW], const float (&b)[1 + DY + DX])
+{
+    float t[1 + DY + DX];
+#pragma unroll
+    for (int m = 0; m < 1 + DY + DX; ++m)
+        t[m] = a[m];
+    return pair_dist<DY, DX>(t, b);
+}
+
+// v_writelane_b32: returns old with lane `lane` replaced by the uniform value v.
+__device__ __forceinline__ uint32_t writelane(uint32_t old, uint32_t v, int lane)
+{
+    // gfx9 allows one SGPR source per VALU op, so the lane select goes in M0.
+    asm("v_writelane_b32 %0, %1, m0" : "+v"(old) : "s"(v), "{m0}"(lane));
+    return old;
+}
+
+// Sorted-list insertion of x into the KP1 smallest values b[0] <= ... <= b[KP1-1]:
+// b0' = min(b0, x), bi' = med3(b(i-1), bi, x).  Leaves the list unchanged when
+// x >= b[KP1-1], so it can run on every lane of the wave.
+template <int KP1>
+__device__ __forceinline__ void insert_sorted(float (&b)[KP1], float x)
+{
+    float prev = b[0];
+    b[0] = fminf(b[0], x);
+#pragma unroll
+    for (int i = 1; i < KP1; ++i) {
+        const float cur = b[i];
+        b[i] = __builtin_amdgcn_fmed3f(prev, cur, x);
+        prev = cur;
+    }
+}
+
+template <int KP1, bool GENERIC>
+__device__ __forceinline__ float kth(const float (&b)[KP1], int k)
+{
+    if (!GENERIC)
+        return b[KP1 - 1];
+    float r = b[0];
+#pragma unroll
+    for (int i = 1; i < KP1; ++i)
+        r = (k == i) ? b[i] : r;
+    return r;
+}
+
+// Work item -> chunk: the largest c with item_start[c] <= q (binary search on
+// scalar loads).
+__device__ __forceinline__ int find_chunk(const int32_t *item_start, int n_chunks, int q)
+{
+    int lo = 0, hi = n_chunks - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (uload_i(item_start + mid) <= q)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------- the search
+
+template <int DY, int DX, int KP1, bool GENERIC, int SLOTS>
+__global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs a)
+{
+    constexpr int D = 1 + DY + DX;
+    constexpr int RW = (D + 1 + 3) & ~3;       // LDS row: D coordinates + radius, 16-byte aligned
+    __shared__ __attribute__((aligned(16))) float rows[kMaxWavesPerWG * kWave * RW];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int k = GENERIC ? a.k : KP1 - 1;
+
+    for (;;) {
+        // ---- claim the next work item (wave-uniform)
+        int q = 0;
+        if (lane == 0)
+            q = atomicAdd(a.counter, 1);
+        q = __builtin_amdgcn_readlane(q, 0);
+        if (q >= a.n_items)
+            break;
+        const int ci = find_chunk(a.item_start, a.n_chunks, q);
+        ChunkDesc cd;
+        {
+            const int64_t *w = reinterpret_cast<const int64_t *>(a.chunks + ci);
+            cd.tp = uload_l(w + 0);
+            cd.s = uload_l(w + 1);
+            cd.ld = uload_l(w + 2);
+            cd.out = uload_l(w + 3);
+            const int32_t *w32 = reinterpret_cast<const int32_t *>(w + 4);
+            cd.n = uload_i(w32 + 0);
+            cd.item0 = uload_i(w32 + 1);
+        }
+        const int n = cd.n;
+        const int r0 = (q - cd.item0) * kWave;
+        const Coords<DY, DX> cp(a.base, cd);
+
+        // ---- pass 1: lane = reference i, candidates uniform
+        const int i = r0 + lane;
+        const bool valid = i < n;
+        const int ii = valid ? i : n - 1;
+        float ref[D];
+#pragma unroll
+        for (int m = 0; m < D; ++m)
+            ref[m] = cp.p[m][ii];
+        float best[KP1];
+#pragma unroll
+        for (int s = 0; s < KP1; ++s)
+            best[s] = kInf;
+        float thr = kInf;
+
+        int j = 0;
+        for (; j + 4 <= n; j += 4) {
+            float c[4][D];
+#pragma unroll
+            for (int m = 0; m < D; ++m) {
+                const f4v v = uload4(cp.p[m] + j);
+                c[0][m] = v.x;
+                c[1][m] = v.y;
+                c[2][m] = v.z;
+                c[3][m] = v.w;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const PairDist<DY, DX> d = pair_dist<DY, DX>(ref, c[u]);
+                const float dj = fmaxf(d.t, fmaxf(d.p, d.s));
+                if (ballot(dj < thr)) {
+                    keep_branch();
+                    insert_sorted<KP1>(best, dj);
+                    thr = kth<KP1, GENERIC>(best, k);
+                }
+            }
+        }
+        for (; j < n; ++j) {
+            float c[D];
+#pragma unroll
+            for (int m = 0; m < D; ++m)
+                c[m] = uload(cp.p[m] + j);
+            const PairDist<DY, DX> d = pair_dist<DY, DX>(ref, c);
+            const float dj = fmaxf(d.t, fmaxf(d.p, d.s));
+            if (ballot(dj < thr)) {
+                keep_branch();
+                insert_sorted<KP1>(best, dj);
+                thr = kth<KP1, GENERIC>(best, k);
+            }
+        }
+        const float eps = thr;   // k+1-th smallest including self = k-th neighbour
+
+        // ---- pass 2: lane = candidate, references uniform
+        // Each lane parks its reference row (coordinates, then the radius) in
+        // this wave's LDS rows; the counting loop reads them back as
+        // wave-wide broadcasts, so a reference costs no SALU address work.
+        float *myrows = rows + (threadIdx.x / kWave) * (kWave * RW);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int m = 0; m < D; ++m)
+            myrows[lane * RW + m] = ref[m];
+        myrows[lane * RW + D] = eps;
+        __builtin_amdgcn_wave_barrier();
+
+        const int nref = min(kWave, n - r0);
+        uint32_t accP = 0, accTP = 0, accPS = 0;
+        for (int t0 = 0; t0 < n; t0 += kWave * SLOTS) {
+            float cand[SLOTS][D];
+#pragma unroll
+            for (int sl = 0; sl < SLOTS; ++sl) {
+                const int idx = t0 + sl * kWave + lane;
+                const bool ok = idx < n;
+                const int ic = ok ? idx : n - 1;       // in-bounds load, padded lanes masked below
+#pragma unroll
+                for (int m = 0; m < D; ++m) {
+                    const float v = cp.p[m][ic];
+                    cand[sl][m] = ok ? v : kInf;
+                }
+            }
+            uint32_t tP = 0, tTP = 0, tPS = 0;
+            for (int r = 0; r < nref; ++r) {
+                float rr[RW];
+                const f4v *rowv = reinterpret_cast<const f4v *>(myrows + r * RW);
+#pragma unroll
+                for (int v = 0; v < RW / 4; ++v) {
+                    const f4v x = rowv[v];
+                    rr[4 * v + 0] = x.x;
+                    rr[4 * v + 1] = x.y;
+                    rr[4 * v + 2] = x.z;
+                    rr[4 * v + 3] = x.w;
+                }
+                const float er = rr[D];
+                uint32_t sP = 0, sTP = 0, sPS = 0;
+#pragma unroll
+                for (int sl = 0; sl < SLOTS; ++sl) {
+                    const PairDist<DY, DX> d = pair_dist_row<DY, DX, RW>(rr, cand[sl]);
+                    const uint64_t mT = ballot(d.t < er);
+                    const uint64_t mP = ballot(d.p < er);
+                    const uint64_t mS = ballot(d.s < er);
+                    sP += (uint32_t)__builtin_popcountll(mP);
+                    sTP += (uint32_t)__builtin_popcountll(mP & mT);
+                    sPS += (uint32_t)__builtin_popcountll(mP & mS);
+                }
+                tP = writelane(tP, sP, r);
+                tTP = writelane(tTP, sTP, r);
+                tPS = writelane(tPS, sPS, r);
+            }
+            accP += tP;
+            accTP += tTP;
+            accPS += tPS;
+        }
+        // self is at distance 0 in every space: counted iff eps > 0
+        const uint32_t self = eps > 0.0f ? 1u : 0u;
+        const int nP = (int)(accP - self), nTP = (int)(accTP - self), nPS = (int)(accPS - self);
+
+        // ---- per-point digamma terms of eq. 9, summed over the item in fixed order
+        double term = 0.0;
+        if (valid)
+            term = psi_of_count(nP) - psi_of_count(nTP) - psi_of_count(nPS);
+        const double sum = wave_sum(term);
+        if (lane == 0)
+            a.partial[q] = sum;
+        if (a.eps_out != nullptr && cd.out >= 0 && valid) {
+            a.eps_out[cd.out + i] = eps;
+            a.cnt_out[cd.out + i] = nP;
+            a.cnt_out[a.cnt_stride + cd.out + i] = nTP;
+            a.cnt_out[2 * a.cnt_stride + cd.out + i] = nPS;
+        }
+    }
+}
+
+// ------------------------------------------------------------ small kernels
+
+__global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = v;
+}
+
+__global__ void embed_kernel(const float *__restrict__ x, const float *__restrict__ y,
+                             const int32_t *__restrict__ perms, const EmbedTask *__restrict__ tasks,
+                             float *__restrict__ base, int R, int T, int d_y, int d_x, int tau, int u,
+                             int32_t *err)
+{
+    const EmbedTask tk = tasks[blockIdx.x];
+    const int n = tk.n;
+    const int64_t pr = (int64_t)tk.pair * R;
+    bool bad = false;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        const int r = q / tk.W;
+        const int t = tk.w + (q - r * tk.W);
+        int rs = r;
+        if (tk.perm >= 0) {
+            rs = perms[tk.perm + r];
+            if (rs < 0 || rs >= tk.Rc) {   // caller error; keep reads in bounds
+                bad = true;
+                rs = r;
+            }
+        }
+        const float *yr = y + (pr + r) * T;
+        const float *xr = x + (pr + rs) * T;
+        if (tk.tp >= 0) {
+            const float v0 = yr[t];
+            bad |= !isfinite(v0);
+            base[tk.tp + q] = v0;
+            for (int m = 0; m < d_y; ++m) {
+                const float v = yr[t - 1 - m * tau];
+                bad |= !isfinite(v);
+                base[tk.tp + (int64_t)(1 + m) * n + q] = v;
+            }
+        }
+        for (int m = 0; m < d_x; ++m) {
+            const float v = xr[t - u - m * tau];
+            bad |= !isfinite(v);
+            base[tk.s + (int64_t)m * n + q] = v;
+        }
+    }
+    if (bad)
+        atomicOr(err, 1);
+}
+
+// Permutation rows must be permutations of 0..Rc-1: one workgroup per row,
+// an LDS bitmap records which values were seen.
+constexpr int kMaxPermTrials = 1 << 16;
+
+__global__ void check_perms_kernel(const int32_t *__restrict__ perms, const int64_t *__restrict__ rows,
+                                   const int32_t *__restrict__ rc, int32_t *err)
+{
+    __shared__ uint32_t seen[kMaxPermTrials / 32];
+    const int Rc = rc[blockIdx.x];
+    const int32_t *row = perms + rows[blockIdx.x];
+    const bool too_big = Rc > kMaxPermTrials;
+    const int words = too_big ? 0 : (Rc + 31) / 32;
+    for (int w = threadIdx.x; w < words; w += blockDim.x)
+        seen[w] = 0;
+    __syncthreads();
+    bool bad = too_big;
+    if (!bad) {
+        for (int r = threadIdx.x; r < Rc; r += blockDim.x) {
+            const int v = row[r];
+            if (v < 0 || v >= Rc) {
+                bad = true;
+            } else {
+                const uint32_t bit = 1u << (v & 31);
+                if (atomicOr(&seen[v >> 5], bit) & bit)
+                    bad = true;
+            }
+        }
+    }
+    if (bad)
+        atomicOr(err, 2);
+}
+
+__global__ void reduce_kernel(const ChunkDesc *__restrict__ chunks, int n_chunks,
+                              const double *__restrict__ partial, int k, const int32_t *err,
+                              double *__restrict__ results)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_chunks)
+        return;
+    const ChunkDesc cd = chunks[c];
+    const int nb = (cd.n + kWave - 1) / kWave;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b)
+        s += partial[cd.item0 + b];
+    double te = psi_of_count(k - 1) + s / (double)cd.n;
+    if (*err != 0)
+        te = __builtin_nan("");
+    results[cd.result] = te;
+}
+
+__global__ void pvalue_kernel(const double *__restrict__ results, int n_groups, int n_surr,
+                              double *__restrict__ pv)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_groups)
+        return;
+    const double *r = results + (int64_t)g * (n_surr + 1);
+    int c = 0;
+    for (int s = 1; s <= n_surr; ++s)
+        c += r[s] >= r[0];
+    pv[g] = n_surr > 0 ? (double)c / (double)n_surr : __builtin_nan("");
+}
+
+// ------------------------------------------------------------- dispatch
+
+typedef void (*search_fn)(SearchArgs);
+
+template <int DY, int DX, int SLOTS>
+struct Table {
+    static search_fn get(bool generic)
+    {
+        return generic ? search_kernel<DY, DX, kMaxK + 1, true, SLOTS>
+                       : search_kernel<DY, DX, 5, false, SLOTS>;
+    }
+};
+
+template <int SLOTS>
+search_fn pick(int d_y, int d_x, bool generic)
+{
+#define TE_CASE(A, B) \
+    if (d_y == A && d_x == B) return Table<A, B, SLOTS>::get(generic);
+    TE_CASE(1, 1) TE_CASE(1, 2) TE_CASE(1, 3) TE_CASE(1, 4)
+    TE_CASE(2, 1) TE_CASE(2, 2) TE_CASE(2, 3) TE_CASE(2, 4)
+    TE_CASE(3, 1) TE_CASE(3, 2) TE_CASE(3, 3) TE_CASE(3, 4)
+    TE_CASE(4, 1) TE_CASE(4, 2) TE_CASE(4, 3) TE_CASE(4, 4)
+#undef TE_CASE
+    return nullptr;
+}
+
+search_fn pick_any(int d_y, int d_x, int k, int slots)
+{
+    const bool generic = (k != 4);
+    if (k < 1 || k > kMaxK)
+        return nullptr;
+    if (slots == 4)
+        return pick<4>(d_y, d_x, generic);
+    if (slots == 8)
+        return pick<8>(d_y, d_x, generic);
+    return nullptr;
+}
+
+}  // namespace
+
+bool search_supported(int d_y, int d_x, int k, int slots) { return pick_any(d_y, d_x, k, slots) != nullptr; }
+
+// Resident workgroups per compute unit for the chosen search variant (0 if unknown).
+int search_occupancy(int d_y, int d_x, int k, int slots, int waves_per_wg)
+{
+    search_fn f = pick_any(d_y, d_x, k, slots);
+    if (!f)
+        return 0;
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, kWave * waves_per_wg, 0) != hipSuccess)
+        return 0;
+    return blocks;
+}
+
+hipError_t launch_search(const SearchArgs &a, int d_y, int d_x, const SearchConfig &cfg, int grid_waves,
+                         hipStream_t st)
+{
+    search_fn f = pick_any(d_y, d_x, a.k, cfg.slots);
+    if (!f)
+        return hipErrorInvalidValue;
+    const int wpg = cfg.waves_per_wg;
+    const int blocks = (grid_waves + wpg - 1) / wpg;
+    hipLaunchKernelGGL(f, dim3(blocks), dim3(kWave * wpg), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_embed(const float *x, const float *y, const int32_t *perms, const EmbedTask *tasks,
+                        int n_tasks, float *base, int R, int T, int d_y, int d_x, int tau, int u,
+                        int32_t *err, hipStream_t st)
+{
+    if (n_tasks <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(embed_kernel, dim3(n_tasks), dim3(256), 0, st, x, y, perms, tasks, base, R, T, d_y,
+                       d_x, tau, u, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_perms(const int32_t *perms, const int64_t *rows, const int32_t *rc, int n_rows,
+                              int32_t *err, hipStream_t st)
+{
+    if (n_rows <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(check_perms_kernel, dim3(n_rows), dim3(256), 0, st, perms, rows, rc, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const ChunkDesc *chunks, int n_chunks, const double *partial, int k,
+                         const int32_t *err, double *results, hipStream_t st)
+{
+    if (n_chunks <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(reduce_kernel, dim3((n_chunks + 127) / 128), dim3(128), 0, st, chunks, n_chunks,
+                       partial, k, err, results);
+    return hipGetLastError();
+}
+
+hipError_t launch_pvalues(const double *results, int n_groups, int n_surr, double *pv, hipStream_t st)
+{
+    if (n_groups <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(pvalue_kernel, dim3((n_groups + 127) / 128), dim3(128), 0, st, results, n_groups,
+                       n_surr, pv);
+    return hipGetLastError();
+}
+
+}  // namespace te

@@ -1,0 +1,109 @@
+// te_runtime.h -- host-side plan, batch and execution state of libte.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "te.h"
+#include "te_internal.h"
+
+namespace te {
+
+te_status fail(te_status st, const char *fmt, ...);
+te_status hip_fail(hipError_t e, const char *what);
+void clear_error();
+te_status current_device(DeviceInfo *out);
+SearchConfig default_config(const DeviceInfo &dev, int d_y, int d_x, int k);
+size_t align_up(size_t v, size_t a);
+
+// A set of chunks laid out in one device workspace, with the host copy of its
+// tables.  Chunks are stored in schedule (longest-first) order.
+struct Batch {
+    std::vector<int> groups;              // (pair * n_points + point) of each group
+    int n_groups = 0;
+    int n_surr = 0;
+    int n_results = 0;                    // n_groups * (n_surr + 1)
+    int64_t n_floats = 0;                 // coordinate storage
+    std::vector<ChunkDesc> chunks;
+    std::vector<int> order;
+    std::vector<int32_t> item_start;
+    std::vector<EmbedTask> tasks;
+    std::vector<int64_t> perm_rows;
+    std::vector<int32_t> perm_rc;
+    int64_t n_items = 0;
+    // byte offsets inside the workspace
+    size_t off_coords = 0, off_tables = 0, off_chunks = 0, off_items = 0, off_tasks = 0, off_prow = 0,
+           off_prc = 0, off_partial = 0, off_results = 0, off_pv = 0, off_ctr = 0;
+    size_t tables_bytes = 0;
+    size_t total_bytes = 0;
+    std::vector<char> host_tables;
+
+    void finish_layout();
+    size_t stage_bytes() const;
+};
+
+// Pinned host staging buffers (table uploads, result downloads), reused across calls.
+struct PinnedPool {
+    struct Buf {
+        void *ptr = nullptr;
+        size_t bytes = 0;
+        bool busy = false;
+    };
+    std::mutex mu;
+    std::vector<Buf> bufs;
+    void *take(size_t bytes);
+    void give(void *ptr);
+    ~PinnedPool();
+};
+
+struct GraphEntry {
+    const void *x = nullptr, *y = nullptr, *perms = nullptr, *ws = nullptr;
+    hipStream_t stream = nullptr;
+    size_t ws_bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<Batch> batches;
+    std::vector<void *> stages;
+};
+
+struct Plan {
+    te_problem p{};
+    std::vector<int32_t> wstart, wlen, trials;
+    std::vector<int64_t> npts;
+    mutable std::mutex dev_mu;
+    mutable bool dev_ready = false;
+    mutable DeviceInfo dev;
+    mutable SearchConfig cfg{};
+    Batch full;
+    size_t min_bytes = 0;
+    size_t plain_bytes = 0;
+
+    mutable PinnedPool pool;
+    mutable std::mutex graph_mu;
+    mutable std::vector<GraphEntry> graphs;
+
+    ~Plan();
+    te_status ensure_device() const;
+    te_status build_group_batch(const std::vector<int> &groups, int n_surr, Batch *b) const;
+    int grid_waves(int64_t n_items) const;
+    te_status enqueue_batch(const Batch &b, const float *x, const float *y, const int32_t *perms, char *ws,
+                            void *stage, hipStream_t st) const;
+    te_status unpack_batch(const Batch &b, const void *stage, double *te_orig, double *te_surr, double *p_value,
+                           bool *bad_input) const;
+    te_status split_batches(size_t ws_bytes, std::vector<Batch> *out) const;
+    te_status run_surrogates(const float *x, const float *y, const int32_t *perms, char *ws, size_t ws_bytes,
+                             hipStream_t st, bool use_graph, double *te_orig, double *te_surr,
+                             double *p_value) const;
+    te_status estimate_plain(const float *x, const float *y, char *ws, size_t ws_bytes, hipStream_t st,
+                             double *te_out) const;
+};
+
+}  // namespace te
+
+struct te_plan_s {
+    te::Plan impl;
+};

@@ -1,0 +1,251 @@
+"""GPU parity: libte (through its C interface) against the CPU oracle.
+
+Bars: radii and the three neighbour counts bit-exact for every point; TE within
+1e-6 nats of the oracle (the required tolerance).  With identical counts the only
+difference left is float64 summation order (about 1e-13), so TE is also checked
+at 1e-9, a level a single differing count (>= 1/N^2, about 4e-8 at N = 5000)
+would exceed.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle
+from synth.rng import derive_key, normal64, uniform01
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+TIGHT = 1e-9
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def te():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1401_4068_amd as te
+    te.lib()
+    return te
+
+
+def dev(wl):
+    import torch
+    x = torch.from_numpy(np.ascontiguousarray(wl.x)).cuda()
+    y = torch.from_numpy(np.ascontiguousarray(wl.y)).cuda()
+    perms = None if wl.perms is None or wl.n_surrogates == 0 else torch.from_numpy(np.ascontiguousarray(wl.perms)).cuda()
+    return x, y, perms
+
+
+# ------------------------------------------------------------ kernel level
+
+def _points(key, N, D, kind):
+    if kind == "gauss":
+        return normal64(key, N * D).reshape(N, D).astype(np.float32)
+    if kind == "grid":
+        return np.floor(uniform01(key, N * D) * 5).reshape(N, D).astype(np.float32)
+    if kind == "dups":
+        base = np.floor(uniform01(key, (N // 4 + 1) * D) * 3).reshape(-1, D)
+        idx = np.floor(uniform01(derive_key(key, 3), N) * base.shape[0]).astype(int)
+        return base[idx].astype(np.float32)
+    if kind == "subnormal":       # differences land in the binary32 subnormal range
+        return (normal64(key, N * D).reshape(N, D) * 2.0 ** -130).astype(np.float32)
+    if kind == "fine":
+        return (1.0 + uniform01(key, N * D).reshape(N, D) * 2.0 ** -18).astype(np.float32)
+    raise ValueError(kind)
+
+
+def _knn_case(te, sizes, d_y, d_x, k, kind, seed=0):
+    import torch
+    D = 1 + d_y + d_x
+    chunks = [_points(derive_key(seed, n, D, k, hash(kind) & 0xFFFF), n, D, kind) for n in sizes]
+    off = np.zeros(len(sizes) + 1, np.int64)
+    off[1:] = np.cumsum(sizes)
+    stride = int(off[-1]) + 37            # coordinate stride larger than the point count
+    soa = np.zeros((D, stride), np.float32)
+    soa[:, :off[-1]] = np.concatenate(chunks).T
+    say("knn case", dict(sizes=sizes, d_y=d_y, d_x=d_x, k=k, kind=kind))
+    eps, cnt, tev = te.knn_counts(torch.from_numpy(soa).cuda(), off, d_y, d_x, k)
+    torch.cuda.synchronize()
+    eps = eps.cpu().numpy()
+    cnt = cnt.cpu().numpy()
+    ref = oracle.counts_batch(chunks, d_y, d_x, k)
+    for c, (re, rc) in enumerate(ref):
+        sl = slice(off[c], off[c + 1])
+        np.testing.assert_array_equal(eps[sl], re.astype(np.float32), err_msg="eps chunk %d" % c)
+        assert np.all(re.astype(np.float32).astype(np.float64) == re)
+        np.testing.assert_array_equal(cnt[:, sl], rc, err_msg="counts chunk %d" % c)
+        t_ref = oracle.te_from_counts(rc, k)
+        assert abs(tev[c] - t_ref) <= TIGHT, (c, tev[c], t_ref)
+
+
+@pytest.mark.parametrize("d_y,d_x", [(1, 1), (2, 2), (3, 3), (4, 4), (1, 4), (3, 2)])
+@pytest.mark.parametrize("kind", ["gauss", "grid", "dups"])
+def test_knn_counts_bit_exact(te, d_y, d_x, kind):
+    _knn_case(te, [5, 64, 65, 127, 300, 1031], d_y, d_x, 4, kind)
+
+
+@pytest.mark.parametrize("k", [1, 2, 7, 15])
+def test_knn_counts_other_k(te, k):
+    _knn_case(te, [k + 1, 70, 513], 2, 3, k, "gauss")
+    _knn_case(te, [k + 1, 200], 3, 3, k, "grid")
+
+
+@pytest.mark.parametrize("kind", ["subnormal", "fine"])
+def test_knn_counts_rounding_edge_values(te, kind):
+    _knn_case(te, [130, 700], 3, 3, 4, kind)
+
+
+def test_knn_counts_large_chunk_multi_tile(te):
+    _knn_case(te, [4100, 2500, 33], 3, 3, 4, "gauss", seed=5)
+
+
+# ------------------------------------------------------------ full estimates
+
+def _compare(wl, te_orig, te_surr=None, pv=None, points=None):
+    ref = oracle.te_workload(wl, points=points)
+    for (p, c, s), r in ref.items():
+        got = te_orig[p, c] if s == 0 else te_surr[p, c, s - 1]
+        assert abs(got - r) <= TOL, ((p, c, s), got, r)
+        assert abs(got - r) <= TIGHT, ((p, c, s), got, r)
+    if pv is not None and wl.n_surrogates:
+        for p in range(wl.n_pairs):
+            for c in (range(wl.n_points) if points is None else points):
+                rs = [ref[(p, c, s)] for s in range(1, wl.n_surrogates + 1)]
+                assert pv[p, c] == oracle.p_value(ref[(p, c, 0)], rs)
+
+
+def test_linear_pair_single_estimate_full_size(te):
+    """Linear Gaussian AR(1) pair, 100 trials x 20-sample window -> N = 2000, D = 5, k = 4."""
+    wl = synth.linear_pair()
+    say("linear pair", wl.chunk_sizes())
+    x, y, _ = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    out = plan.estimate(x, y)
+    _compare(wl, out)
+    t0, _, pv = plan.surrogates(x, y)
+    assert t0[0, 0] == out[0, 0]
+    assert math.isnan(pv[0, 0])
+
+
+def test_uneven_chunks_with_surrogates(te):
+    wl = synth.uneven_surrogates(R=300, T=60, n_points=6, n_surrogates=7, n_lo=100, n_hi=2600)
+    say("uneven", wl.chunk_sizes(), wl.trials, wl.window_len)
+    x, y, perms = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    t0, ts, pv = plan.surrogates(x, y, perms)
+    _compare(wl, t0, ts, pv)
+
+
+def test_meg_like_pairs_tau2(te):
+    wl = synth.meg_like(n_pairs=3, R=20, T=160, n_points=4, n_surrogates=3, on=60, off=120)
+    say("meg-like", wl.chunk_sizes())
+    x, y, perms = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    t0, ts, pv = plan.surrogates(x, y, perms)
+    _compare(wl, t0, ts, pv)
+    plain = plan.estimate(x, y)
+    np.testing.assert_array_equal(plain, t0)
+
+
+def test_nonlinear_full_size_sampled(te):
+    """500 trials x 300 samples, 100 windows of 10 samples (N = 5000, D = 7): all windows on the
+    GPU, both paths; the oracle checks a seeded sample of windows."""
+    wl = synth.nonlinear_ensemble()
+    say("nonlinear full", wl.n_points, wl.chunk_sizes()[0])
+    x, y, _ = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    t0, _, _ = plan.surrogates(x, y)
+    plain = plan.estimate(x, y)
+    np.testing.assert_array_equal(plain, t0)
+    pts = sorted(set(np.floor(uniform01(derive_key(99), 6) * wl.n_points).astype(int).tolist()) | {0, 99})
+    _compare(wl, t0, points=pts)
+
+
+def test_split_workspace_gives_identical_results(te):
+    import torch
+    wl = synth.uneven_surrogates(R=200, T=60, n_points=5, n_surrogates=4, n_lo=100, n_hi=1500)
+    x, y, perms = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    full, mn, _ = plan.workspace_bytes()
+    a = plan.surrogates(x, y, perms)
+    ws_small = torch.empty(mn, dtype=torch.uint8, device="cuda")
+    say("split", full, mn)
+    b = plan.surrogates(x, y, perms, ws=ws_small)
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+
+
+def test_graph_replay_matches_eager(te):
+    import torch
+    wl = synth.uneven_surrogates(R=120, T=60, n_points=3, n_surrogates=5, n_lo=100, n_hi=1200)
+    x, y, perms = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    eager = plan.surrogates(x, y, perms)
+    s = torch.cuda.Stream()
+    for rep in range(4):
+        say("graph replay", rep)
+        g = plan.surrogates(x, y, perms, stream=s, use_graph=True)
+        for u, v in zip(eager, g):
+            np.testing.assert_array_equal(u, v)
+        # unrelated eager work between replays
+        z = torch.randn(1 << 16, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert torch.isfinite(z)
+
+
+def test_runs_are_bitwise_reproducible(te):
+    wl = synth.uneven_surrogates(R=150, T=60, n_points=4, n_surrogates=3, n_lo=300, n_hi=1500)
+    x, y, perms = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    a = plan.surrogates(x, y, perms)
+    b = plan.surrogates(x, y, perms)
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+
+
+def test_identity_surrogates_equal_original(te):
+    import torch
+    wl = synth.generic((12,), R=30, T=40, starts=(20,), windows=(10,), n_surrogates=3)
+    wl.perms[:] = np.arange(wl.n_trials, dtype=np.int32)
+    x, y, perms = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    t0, ts, pv = plan.surrogates(x, y, perms)
+    assert np.all(ts[0, 0] == t0[0, 0])
+    assert pv[0, 0] == 1.0
+
+
+def test_nonfinite_input_is_rejected(te):
+    import torch
+    wl = synth.generic((13,), R=30, T=40, starts=(20,), windows=(10,))
+    wl.y[0, 3, 17] = np.nan          # inside the embedding of window [20, 30) via the target past
+    x, y, _ = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    with pytest.raises(te.TEError) as ei:
+        plan.estimate(x, y)
+    assert ei.value.status == 1
+    with pytest.raises(te.TEError):
+        plan.surrogates(x, y)
+
+
+def test_invalid_permutation_is_rejected(te):
+    import torch
+    wl = synth.generic((14,), R=30, T=40, starts=(20,), windows=(10,), n_surrogates=2)
+    wl.perms[0, 0, 1, 4] = wl.perms[0, 0, 1, 5]      # duplicate entry
+    x, y, perms = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    with pytest.raises(te.TEError) as ei:
+        plan.surrogates(x, y, perms)
+    assert ei.value.status == 1
+    wl.perms[0, 0, 1, 4] = 30                        # out of range
+    x, y, perms = dev(wl)
+    with pytest.raises(te.TEError):
+        plan.surrogates(x, y, perms)

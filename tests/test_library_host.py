@@ -1,0 +1,86 @@
+"""Host-side checks of libte that need no GPU: exported symbols and plan validation."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "te.h")
+
+
+def _lib_or_build():
+    from paper_1401_4068_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1401_4068_amd import build
+        build.build()
+    return _lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(te_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    _lib = _lib_or_build()
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    names = declared_functions()
+    assert "te_plan_create" in names and "te_knn_counts" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) <= set(_lib.SIGNATURES), set(names) - set(_lib.SIGNATURES)
+
+
+def _plan(**kw):
+    from paper_1401_4068_amd import Plan
+    args = dict(n_pairs=1, n_trials=20, n_samples=50, d_y=2, d_x=2, tau=1, u=1, k=4, window_start=[10],
+                window_len=[10], trials=None, n_surrogates=0)
+    args.update(kw)
+    return Plan(**args)
+
+
+def test_plan_sizes_without_gpu():
+    _lib_or_build()
+    p = _plan(n_surrogates=5, window_start=[10, 20, 30], window_len=[10, 5, 8], trials=[20, 10, 15])
+    full, mn, plain = p.workspace_bytes()
+    assert full >= mn > 0 and plain > 0
+    # coordinate storage alone: per window (1 + d_y) N + (S + 1) d_x N floats
+    N = np.array([200, 50, 120])
+    assert full >= 4 * np.sum(N * 3 + 6 * N * 2)
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (dict(d_y=0), "d_y and d_x"),
+    (dict(d_x=5), "d_y and d_x"),
+    (dict(k=0), "k must be"),
+    (dict(k=16), "k must be"),
+    (dict(tau=0), "tau and u"),
+    (dict(u=0), "tau and u"),
+    (dict(window_start=[1]), "history"),                       # needs 2 samples of history
+    (dict(window_start=[45], window_len=[10]), "past n_samples"),
+    (dict(window_len=[0]), "length"),
+    (dict(trials=[21]), "trials"),
+    (dict(trials=[1], window_len=[4]), "need more than k"),     # N = 4 <= k
+    (dict(n_surrogates=-1), "n_surrogates"),
+])
+def test_plan_rejects_invalid_geometry(bad, msg):
+    from paper_1401_4068_amd import TEError
+    _lib_or_build()
+    with pytest.raises(TEError) as ei:
+        _plan(**bad)
+    assert ei.value.status == 1 and msg in str(ei.value)
+
+
+def test_history_rule_matches_embedding():
+    # d_y = 4, d_x = 4, tau = 2, u = 5: history = max(1 + 3*2, 5 + 3*2) = 11
+    assert synth.history(4, 4, 2, 5) == 11
+    _lib_or_build()
+    _plan(d_y=4, d_x=4, tau=2, u=5, window_start=[11])
+    from paper_1401_4068_amd import TEError
+    with pytest.raises(TEError):
+        _plan(d_y=4, d_x=4, tau=2, u=5, window_start=[10])

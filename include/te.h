@@ -145,6 +145,14 @@ te_status te_knn_counts(const float *pts, int64_t dim_stride, const int64_t *off
                         void *ws, size_t ws_bytes, void *hip_stream,
                         float *eps, int32_t *counts, double *te_out);
 
+/* Measurement hook.  While enabled, every search-kernel launch made by
+ * te_estimate, te_surrogates and te_knn_counts outside graph capture is
+ * bracketed by HIP events recorded on the launch stream.  te_profile_read
+ * waits for those events and returns the summed kernel time in milliseconds
+ * and the number of launches (reset != 0 clears the totals).  Process-wide. */
+te_status te_profile_enable(int32_t on);
+te_status te_profile_read(double *search_ms, int64_t *launches, int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,7 +6,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libte.so")
+# TE_LIB_PATH selects another build of the same library (e.g. a tuning variant).
+LIB_PATH = os.environ.get("TE_LIB_PATH") or os.path.join(HERE, "libte.so")
 
 TE_OK, TE_ERR_INVALID, TE_ERR_NOMEM, TE_ERR_DEVICE, TE_ERR_BUSY, TE_ERR_TIMEOUT, TE_ERR_CANCELLED = range(7)
 STATUS_NAMES = {0: "TE_OK", 1: "TE_ERR_INVALID", 2: "TE_ERR_NOMEM", 3: "TE_ERR_DEVICE", 4: "TE_ERR_BUSY",
@@ -48,6 +49,8 @@ SIGNATURES = {
     "te_estimate": ([_vp, _vp, _vp, _vp, _sz, _vp, _dp], _st),
     "te_surrogates": ([_vp, _vp, _vp, _vp, _vp, _sz, _vp, _i32, _dp, _dp, _dp], _st),
     "te_knn_counts_workspace_bytes": ([_i32, _i64], _sz),
+    "te_profile_enable": ([_i32], _st),
+    "te_profile_read": ([_dp, ctypes.POINTER(_i64), _i32], _st),
     "te_knn_counts": ([_vp, _i64, ctypes.POINTER(_i64), _i32, _i32, _i32, _i32, _vp, _sz, _vp, _vp, _vp, _dp], _st),
 }
 

@@ -183,5 +183,18 @@ def knn_counts(pts, offsets, d_y, d_x, k, stream=None, ws=None, want_te=True):
     return eps[:total], cnt[:, :total], te
 
 
+def profile_enable(on: bool = True):
+    """Bracket search-kernel launches with HIP events (te_profile_enable)."""
+    check(lib().te_profile_enable(int(bool(on))))
+
+
+def profile_read(reset: bool = False):
+    """(summed search-kernel milliseconds, launches) since the last reset."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    check(lib().te_profile_read(ctypes.byref(ms), ctypes.byref(n), int(bool(reset))))
+    return ms.value, n.value
+
+
 def version() -> str:
     return lib().te_version().decode()

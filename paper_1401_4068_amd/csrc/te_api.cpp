@@ -299,7 +299,7 @@ te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, co
     a.eps_out = nullptr;
     a.cnt_out = nullptr;
     a.cnt_stride = 0;
-    if ((e = launch_search(a, p.d_y, p.d_x, cfg, grid_waves(b.n_items), st)) != hipSuccess)
+    if ((e = launch_search_timed(a, p.d_y, p.d_x, cfg, grid_waves(b.n_items), st)) != hipSuccess)
         return hip_fail(e, "search launch");
     double *res = reinterpret_cast<double *>(ws + b.off_results);
     if ((e = launch_reduce(a.chunks, a.n_chunks, a.partial, p.k, ctr + 1, res, st)) != hipSuccess)

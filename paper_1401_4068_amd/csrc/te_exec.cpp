@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -17,14 +18,24 @@ namespace te {
 
 int search_occupancy(int d_y, int d_x, int k, int slots, int waves_per_wg);
 
+static int env_int(const char *name, int dflt)
+{
+    const char *v = std::getenv(name);
+    return (v && *v) ? std::atoi(v) : dflt;
+}
+
+// Launch shape of the search kernel.  TE_SLOTS and TE_WG_PER_CU override the
+// defaults (used by the tuner and for measurements).
 SearchConfig default_config(const DeviceInfo &dev, int d_y, int d_x, int k)
 {
     (void)dev;
     SearchConfig c;
-    c.slots = 8;
+    c.slots = env_int("TE_SLOTS", 8);
+    if (c.slots != 4 && c.slots != 8 && c.slots != 16)
+        c.slots = 8;
     c.waves_per_wg = 4;
     const int occ = search_occupancy(d_y, d_x, k, c.slots, c.waves_per_wg);
-    c.wg_per_cu = std::max(1, occ);
+    c.wg_per_cu = std::max(1, env_int("TE_WG_PER_CU", occ));
     return c;
 }
 
@@ -252,7 +263,7 @@ te_status Plan::estimate_plain(const float *x, const float *y, char *ws, size_t 
         a.k = p.k;
         a.counter = ctr + 4 * g;
         a.partial = partial;
-        e = launch_search(a, p.d_y, p.d_x, cfg, grid_waves(items), st);
+        e = launch_search_timed(a, p.d_y, p.d_x, cfg, grid_waves(items), st);
         if (e != hipSuccess)
             break;
         e = launch_reduce(dc + g, 1, partial, p.k, ctr + 4 * g + 1, res, st);
@@ -381,7 +392,7 @@ te_status te_knn_counts(const float *pts, int64_t dim_stride, const int64_t *off
     a.cnt_stride = total;
     if (e == hipSuccess) {
         const int64_t full = (int64_t)dev.n_cu * cfg.wg_per_cu * cfg.waves_per_wg;
-        e = launch_search(a, d_y, d_x, cfg, (int)std::max<int64_t>(1, std::min<int64_t>(full, items)), st);
+        e = launch_search_timed(a, d_y, d_x, cfg, (int)std::max<int64_t>(1, std::min<int64_t>(full, items)), st);
     }
     double *res = reinterpret_cast<double *>(ws + off_results);
     if (e == hipSuccess)

@@ -84,4 +84,8 @@ hipError_t launch_reduce(const ChunkDesc *chunks, int n_chunks, const double *pa
 hipError_t launch_pvalues(const double *results, int n_groups, int n_surr, double *pv, hipStream_t st);
 bool search_supported(int d_y, int d_x, int k, int slots);
 
+// Search launch bracketed by profiling events when measurement is enabled (te_profile.cpp).
+hipError_t launch_search_timed(const SearchArgs &a, int d_y, int d_x, const SearchConfig &cfg, int grid_waves,
+                               hipStream_t st);
+
 }  // namespace te

@@ -147,19 +147,20 @@ __device__ __forceinline__ uint32_t writelane(uint32_t old, uint32_t v, int lane
 }
 
 // Sorted-list insertion of x into the KP1 smallest values b[0] <= ... <= b[KP1-1]:
-// b0' = min(b0, x), bi' = med3(b(i-1), bi, x).  Leaves the list unchanged when
-// x >= b[KP1-1], so it can run on every lane of the wave.
+// from the top down, bi' = med3(b(i-1), bi, x), then b0' = min(b0, x).  Each
+// step reads only entries not yet updated, so the list is rewritten in place
+// (KP1 VALU ops, no copies).  Leaves the list unchanged when x >= b[KP1-1], so
+// it can run on every lane of the wave.  All values are non-negative floats
+// (+0 .. +inf), whose bit patterns order like unsigned integers; the minimum
+// is taken on the bits (no NaN canonicalisation needed).
 template <int KP1>
 __device__ __forceinline__ void insert_sorted(float (&b)[KP1], float x)
 {
-    float prev = b[0];
-    b[0] = fminf(b[0], x);
 #pragma unroll
-    for (int i = 1; i < KP1; ++i) {
-        const float cur = b[i];
-        b[i] = __builtin_amdgcn_fmed3f(prev, cur, x);
-        prev = cur;
-    }
+    for (int i = KP1 - 1; i >= 1; --i)
+        b[i] = __builtin_amdgcn_fmed3f(b[i - 1], b[i], x);
+    const uint32_t lo = min(__builtin_bit_cast(uint32_t, b[0]), __builtin_bit_cast(uint32_t, x));
+    b[0] = __builtin_bit_cast(float, lo);
 }
 
 template <int KP1, bool GENERIC>
@@ -253,10 +254,11 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
             for (int u = 0; u < 4; ++u) {
                 const PairDist<DY, DX> d = pair_dist<DY, DX>(ref, c[u]);
                 const float dj = fmaxf(d.t, fmaxf(d.p, d.s));
-                if (ballot(dj < thr)) {
+                if (ballot(dj < (GENERIC ? thr : best[KP1 - 1]))) {
                     keep_branch();
                     insert_sorted<KP1>(best, dj);
-                    thr = kth<KP1, GENERIC>(best, k);
+                    if (GENERIC)
+                        thr = kth<KP1, GENERIC>(best, k);
                 }
             }
         }
@@ -267,13 +269,15 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                 c[m] = uload(cp.p[m] + j);
             const PairDist<DY, DX> d = pair_dist<DY, DX>(ref, c);
             const float dj = fmaxf(d.t, fmaxf(d.p, d.s));
-            if (ballot(dj < thr)) {
+            if (ballot(dj < (GENERIC ? thr : best[KP1 - 1]))) {
                 keep_branch();
                 insert_sorted<KP1>(best, dj);
-                thr = kth<KP1, GENERIC>(best, k);
+                if (GENERIC)
+                    thr = kth<KP1, GENERIC>(best, k);
             }
         }
-        const float eps = thr;   // k+1-th smallest including self = k-th neighbour
+        // k+1-th smallest including self (distance 0) = k-th neighbour without self
+        const float eps = GENERIC ? thr : best[KP1 - 1];
 
         // ---- pass 2: lane = candidate, references uniform
         // Each lane parks its reference row (coordinates, then the radius) in
@@ -503,6 +507,8 @@ search_fn pick_any(int d_y, int d_x, int k, int slots)
         return pick<4>(d_y, d_x, generic);
     if (slots == 8)
         return pick<8>(d_y, d_x, generic);
+    if (slots == 16)
+        return pick<16>(d_y, d_x, generic);
     return nullptr;
 }
 

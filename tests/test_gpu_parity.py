@@ -226,12 +226,22 @@ def test_identity_surrogates_equal_original(te):
 def test_nonfinite_input_is_rejected(te):
     import torch
     wl = synth.generic((13,), R=30, T=40, starts=(20,), windows=(10,))
-    wl.y[0, 3, 17] = np.nan          # inside the embedding of window [20, 30) via the target past
+    # window [20, 30) with d_y = d_x = 2, tau = 1, u = 1 reads samples 18..29 only
+    wl.y[0, 3, 17] = np.nan
+    wl.x[0, 5, 3] = np.inf
     x, y, _ = dev(wl)
     plan = te.Plan.from_workload(wl)
+    assert np.isfinite(plan.estimate(x, y)).all()          # values outside the windows are never read
+    wl.y[0, 3, 25] = np.nan                                 # target future of point (3, 25)
+    x, y, _ = dev(wl)
     with pytest.raises(te.TEError) as ei:
         plan.estimate(x, y)
     assert ei.value.status == 1
+    with pytest.raises(te.TEError):
+        plan.surrogates(x, y)
+    wl.y[0, 3, 25] = 1.0
+    wl.x[0, 7, 18] = -np.inf                                # source past of point (7, 19)
+    x, y, _ = dev(wl)
     with pytest.raises(te.TEError):
         plan.surrogates(x, y)
 

@@ -145,6 +145,66 @@ te_status te_knn_counts(const float *pts, int64_t dim_stride, const int64_t *off
                         void *ws, size_t ws_bytes, void *hip_stream,
                         float *eps, int32_t *counts, double *te_out);
 
+/* ------------------------------------------------------------------ serving
+ * A server keeps admitted jobs resident in a caller-provided device arena and
+ * batches their searches continuously: a server thread admits queued jobs in
+ * FIFO order while a job slot is free and the job's footprint (series,
+ * permutations, embedded coordinates, tables, partial sums) fits in the arena,
+ * embeds each admitted job once, and issues steps -- one persistent search
+ * launch per kernel class (d_y, d_x, k) over reference blocks of all ready jobs,
+ * oldest first, up to step_pairs directed pairs -- so jobs arriving while others
+ * run join at the next step.  Estimates are reduced per job in a fixed order and
+ * do not depend on which jobs shared a step.  Same semantics as te_surrogates. */
+
+#define TE_SERVE_DRY_RUN 1   /* admission and scheduling only: no device work, results NaN */
+#define TE_SERVE_HOLD 2      /* queue submissions without admitting them until te_serve_resume */
+
+typedef struct {
+    double p50_s, p99_s;      /* latency quantiles, submit -> result, completed jobs  */
+    double est_per_s;         /* estimates (originals + surrogates) per second since
+                                 the first submission                                 */
+    int64_t completed, failed, cancelled;
+    int64_t steps;            /* search launches issued                               */
+    int64_t queued, resident; /* jobs waiting for admission / admitted, now           */
+    int64_t peak_slots;       /* most jobs resident at once                           */
+    int64_t peak_bytes;       /* most arena bytes in use at once                      */
+} te_serve_stats_t;
+
+/* Open a server on the current device.
+ *   arena        device memory of arena_bytes owned by the caller, kept alive until
+ *                te_serve_close returns (may be NULL with TE_SERVE_DRY_RUN)
+ *   max_slots    jobs resident at once (>= 1); max_queue: jobs waiting (>= 1)
+ *   step_pairs   directed pairs per search launch (0: 4e9, a few milliseconds)
+ *   flags        0, TE_SERVE_DRY_RUN and/or TE_SERVE_HOLD */
+te_status te_serve_open(void *arena, size_t arena_bytes, int32_t max_slots, int32_t max_queue,
+                        int64_t step_pairs, int32_t flags, te_server *out);
+
+/* Submit a job (non-blocking; any thread).  x, y: host float32
+ * [n_pairs][n_trials][n_samples]; perms: host int32 [n_pairs][n_points][S][n_trials]
+ * (NULL if S == 0).  Everything is copied before return.  TE_ERR_INVALID: bad
+ * problem; TE_ERR_NOMEM: the job can never fit the arena; TE_ERR_BUSY: queue full. */
+te_status te_serve_submit(te_server srv, const te_problem *problem, const float *x, const float *y,
+                          const int32_t *perms, uint64_t *ticket);
+
+/* Wait for a ticket: timeout_us < 0 waits forever, 0 polls.  On TE_OK writes the
+ * host outputs (te_orig [n_pairs][n_points]; te_surr [..][S] and p_value may be
+ * NULL) and releases the ticket; TE_ERR_TIMEOUT leaves it pending; a failed or
+ * cancelled ticket returns its status and is released. */
+te_status te_serve_wait(te_server srv, uint64_t ticket, int64_t timeout_us,
+                        double *te_orig, double *te_surr, double *p_value);
+
+/* Start admitting jobs on a server opened with TE_SERVE_HOLD. */
+te_status te_serve_resume(te_server srv);
+
+/* Cancel a ticket that has not been admitted yet (TE_ERR_BUSY once admitted). */
+te_status te_serve_cancel(te_server srv, uint64_t ticket);
+
+te_status te_serve_stats(te_server srv, te_serve_stats_t *out);
+
+/* Stop accepting jobs, cancel queued ones, finish admitted ones, join the server
+ * thread and free the server.  The arena may be freed afterwards. */
+te_status te_serve_close(te_server srv);
+
 /* Measurement hook.  While enabled, every search-kernel launch made by
  * te_estimate, te_surrogates and te_knn_counts outside graph capture is
  * bracketed by HIP events recorded on the launch stream.  te_profile_read

@@ -30,6 +30,16 @@ class Problem(ctypes.Structure):
     ]
 
 
+class ServeStats(ctypes.Structure):
+    _fields_ = [("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double), ("est_per_s", ctypes.c_double),
+                ("completed", ctypes.c_int64), ("failed", ctypes.c_int64), ("cancelled", ctypes.c_int64),
+                ("steps", ctypes.c_int64), ("queued", ctypes.c_int64), ("resident", ctypes.c_int64),
+                ("peak_slots", ctypes.c_int64), ("peak_bytes", ctypes.c_int64)]
+
+
+TE_SERVE_DRY_RUN = 1
+TE_SERVE_HOLD = 2
+
 _lib = None
 
 _vp = ctypes.c_void_p
@@ -51,6 +61,13 @@ SIGNATURES = {
     "te_knn_counts_workspace_bytes": ([_i32, _i64], _sz),
     "te_profile_enable": ([_i32], _st),
     "te_profile_read": ([_dp, ctypes.POINTER(_i64), _i32], _st),
+    "te_serve_open": ([_vp, _sz, _i32, _i32, _i64, _i32, ctypes.POINTER(_vp)], _st),
+    "te_serve_submit": ([_vp, ctypes.POINTER(Problem), _vp, _vp, _vp, ctypes.POINTER(ctypes.c_uint64)], _st),
+    "te_serve_wait": ([_vp, ctypes.c_uint64, _i64, _dp, _dp, _dp], _st),
+    "te_serve_resume": ([_vp], _st),
+    "te_serve_cancel": ([_vp, ctypes.c_uint64], _st),
+    "te_serve_stats": ([_vp, ctypes.POINTER(ServeStats)], _st),
+    "te_serve_close": ([_vp], _st),
     "te_knn_counts": ([_vp, _i64, ctypes.POINTER(_i64), _i32, _i32, _i32, _i32, _vp, _sz, _vp, _vp, _vp, _dp], _st),
 }
 

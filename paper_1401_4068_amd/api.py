@@ -9,7 +9,7 @@ import ctypes
 
 import numpy as np
 
-from ._lib import Problem, check, lib
+from ._lib import TE_SERVE_DRY_RUN, TE_SERVE_HOLD, Problem, ServeStats, check, lib
 
 
 def _torch():
@@ -42,6 +42,31 @@ def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
+def _problem(n_pairs, n_trials, n_samples, d_y, d_x, tau, u, k, window_start, window_len=None, trials=None,
+             n_surrogates=0, window=0):
+    """A te_problem and the arrays it points to (keep both alive while it is used)."""
+    keep = []
+    ws = np.ascontiguousarray(window_start, np.int32)
+    p = Problem()
+    p.n_pairs, p.n_trials, p.n_samples = n_pairs, n_trials, n_samples
+    p.d_y, p.d_x, p.tau, p.u, p.k = d_y, d_x, tau, u, k
+    p.n_points = int(ws.shape[0])
+    p.window = int(window)
+    p.n_surrogates = int(n_surrogates)
+    I32P = ctypes.POINTER(ctypes.c_int32)
+    p.window_start = ws.ctypes.data_as(I32P)
+    keep.append(ws)
+    if window_len is not None:
+        wl = np.ascontiguousarray(window_len, np.int32)
+        p.window_len = wl.ctypes.data_as(I32P)
+        keep.append(wl)
+    if trials is not None:
+        tr = np.ascontiguousarray(trials, np.int32)
+        p.trials = tr.ctypes.data_as(I32P)
+        keep.append(tr)
+    return p, keep
+
+
 class Plan:
     """An analysis plan (te_plan): geometry of one job, validated on creation.
 
@@ -53,28 +78,11 @@ class Plan:
 
     def __init__(self, n_pairs, n_trials, n_samples, d_y, d_x, tau, u, k, window_start, window_len=None,
                  trials=None, n_surrogates=0, window=0):
-        self._keep = []
-        ws = np.ascontiguousarray(window_start, np.int32)
-        self.n_points = int(ws.shape[0])
+        p, self._keep = _problem(n_pairs, n_trials, n_samples, d_y, d_x, tau, u, k, window_start, window_len,
+                                 trials, n_surrogates, window)
+        self.n_points = int(p.n_points)
         self.n_pairs = int(n_pairs)
         self.n_surrogates = int(n_surrogates)
-        p = Problem()
-        p.n_pairs, p.n_trials, p.n_samples = n_pairs, n_trials, n_samples
-        p.d_y, p.d_x, p.tau, p.u, p.k = d_y, d_x, tau, u, k
-        p.n_points = self.n_points
-        p.window = int(window)
-        p.n_surrogates = int(n_surrogates)
-        I32P = ctypes.POINTER(ctypes.c_int32)
-        p.window_start = ws.ctypes.data_as(I32P)
-        self._keep.append(ws)
-        if window_len is not None:
-            wl = np.ascontiguousarray(window_len, np.int32)
-            p.window_len = wl.ctypes.data_as(I32P)
-            self._keep.append(wl)
-        if trials is not None:
-            tr = np.ascontiguousarray(trials, np.int32)
-            p.trials = tr.ctypes.data_as(I32P)
-            self._keep.append(tr)
         h = ctypes.c_void_p()
         check(lib().te_plan_create(ctypes.byref(p), ctypes.byref(h)))
         self._h = h
@@ -154,6 +162,79 @@ class Plan:
                                   wsp, wsn, sh, int(bool(use_graph)), _dp(te_orig),
                                   _dp(te_surr) if S > 0 else None, _dp(pv)))
         return te_orig, te_surr, pv
+
+
+class Server:
+    """Continuous-batching server (te_serve_*): jobs are submitted with host arrays and
+    run on a device arena allocated here (a torch uint8 tensor) unless dry_run."""
+
+    def __init__(self, arena_bytes, max_slots=64, max_queue=1 << 20, step_pairs=0, dry_run=False, hold=False):
+        self._arena = None
+        ptr = ctypes.c_void_p(0)
+        if not dry_run:
+            torch = _torch()
+            self._arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
+            ptr = ctypes.c_void_p(self._arena.data_ptr())
+        flags = (TE_SERVE_DRY_RUN if dry_run else 0) | (TE_SERVE_HOLD if hold else 0)
+        h = ctypes.c_void_p()
+        check(lib().te_serve_open(ptr, int(arena_bytes), int(max_slots), int(max_queue), int(step_pairs), flags,
+                                  ctypes.byref(h)))
+        self._h = h
+        self._shapes = {}
+
+    def submit(self, wl):
+        """Submit a synth Workload-like object (series, geometry, perms); returns a ticket."""
+        p, keep = _problem(wl.n_pairs, wl.n_trials, wl.n_samples, wl.d_y, wl.d_x, wl.tau, wl.u, wl.k,
+                           wl.window_start, wl.window_len, wl.trials, wl.n_surrogates)
+        x = np.ascontiguousarray(wl.x, np.float32)
+        y = np.ascontiguousarray(wl.y, np.float32)
+        perms = None
+        if wl.n_surrogates > 0:
+            perms = np.ascontiguousarray(wl.perms, np.int32)
+            if perms.size != wl.n_pairs * wl.n_points * wl.n_surrogates * wl.n_trials:
+                raise ValueError("perms must be [n_pairs, n_points, S, n_trials]")
+        t = ctypes.c_uint64()
+        check(lib().te_serve_submit(self._h, ctypes.byref(p), ctypes.c_void_p(x.ctypes.data),
+                                    ctypes.c_void_p(y.ctypes.data),
+                                    None if perms is None else ctypes.c_void_p(perms.ctypes.data), ctypes.byref(t)))
+        self._shapes[t.value] = (wl.n_pairs, int(p.n_points), wl.n_surrogates)
+        return t.value
+
+    def wait(self, ticket, timeout_s=None):
+        """(te_orig [P, C], te_surr [P, C, S], p_value [P, C]) of a finished ticket."""
+        P, C, S = self._shapes[ticket]
+        te_orig = np.empty((P, C), np.float64)
+        te_surr = np.empty((P, C, max(S, 0)), np.float64)
+        pv = np.empty((P, C), np.float64)
+        us = -1 if timeout_s is None else int(timeout_s * 1e6)
+        st = lib().te_serve_wait(self._h, ctypes.c_uint64(ticket), us, _dp(te_orig), _dp(te_surr) if S > 0 else None,
+                                 _dp(pv))
+        if st != 5:     # anything but a timeout releases the ticket
+            self._shapes.pop(ticket, None)
+        check(st)
+        return te_orig, te_surr, pv
+
+    def resume(self):
+        check(lib().te_serve_resume(self._h))
+
+    def cancel(self, ticket):
+        check(lib().te_serve_cancel(self._h, ctypes.c_uint64(ticket)))
+
+    def stats(self):
+        s = ServeStats()
+        check(lib().te_serve_stats(self._h, ctypes.byref(s)))
+        return {name: getattr(s, name) for name, _ in ServeStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            check(lib().te_serve_close(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def knn_counts(pts, offsets, d_y, d_x, k, stream=None, ws=None, want_te=True):

@@ -97,6 +97,8 @@ void Batch::finish_layout()
     for (int c : order) {
         ChunkDesc d = chunks[c];
         d.item0 = (int32_t)n_items;
+        d.block0 = 0;
+        d.pbase = n_items;
         n_items += (d.n + kWave - 1) / kWave;
         item_start.push_back(d.item0);
         sorted.push_back(d);

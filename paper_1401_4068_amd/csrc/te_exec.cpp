@@ -223,6 +223,8 @@ te_status Plan::estimate_plain(const float *x, const float *y, char *ws, size_t 
         d.out = -1;
         d.n = N;
         d.item0 = 0;
+        d.block0 = 0;
+        d.pbase = 0;
         d.result = g;
         hc[g] = d;
         hi[g] = 0;
@@ -345,6 +347,8 @@ te_status te_knn_counts(const float *pts, int64_t dim_stride, const int64_t *off
     for (int i = 0; i < n_chunks; ++i) {
         sorted[i] = chunks[order[i]];
         sorted[i].item0 = (int32_t)items;
+        sorted[i].block0 = 0;
+        sorted[i].pbase = items;
         starts[i] = (int32_t)items;
         items += (sorted[i].n + kWave - 1) / kWave;
     }

@@ -24,10 +24,11 @@ struct ChunkDesc {
     int64_t s;        // float offset of the source block
     int64_t ld;       // stride between coordinates, in floats
     int64_t out;      // per-point output offset (eps / counts), or -1
+    int64_t pbase;    // index in the partial-sum array of the chunk's block 0
     int32_t n;        // points in the chunk
-    int32_t item0;    // index of the chunk's first work item (64 references each)
+    int32_t item0;    // launch work-item index of the first scheduled block
+    int32_t block0;   // first scheduled block (64 references) of the chunk
     int32_t result;   // slot of the chunk's estimate in the result array
-    int32_t pad_;
 };
 
 // Work for the embedding kernel: writes one chunk's source block, and the

@@ -30,6 +30,7 @@
 
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "te_internal.h"
@@ -212,17 +213,19 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
         const int ci = find_chunk(a.item_start, a.n_chunks, q);
         ChunkDesc cd;
         {
-            const int64_t *w = reinterpret_cast<const int64_t *>(a.chunks + ci);
-            cd.tp = uload_l(w + 0);
-            cd.s = uload_l(w + 1);
-            cd.ld = uload_l(w + 2);
-            cd.out = uload_l(w + 3);
-            const int32_t *w32 = reinterpret_cast<const int32_t *>(w + 4);
-            cd.n = uload_i(w32 + 0);
-            cd.item0 = uload_i(w32 + 1);
+            const char *w = reinterpret_cast<const char *>(a.chunks + ci);
+            cd.tp = uload_l(reinterpret_cast<const int64_t *>(w + offsetof(ChunkDesc, tp)));
+            cd.s = uload_l(reinterpret_cast<const int64_t *>(w + offsetof(ChunkDesc, s)));
+            cd.ld = uload_l(reinterpret_cast<const int64_t *>(w + offsetof(ChunkDesc, ld)));
+            cd.out = uload_l(reinterpret_cast<const int64_t *>(w + offsetof(ChunkDesc, out)));
+            cd.pbase = uload_l(reinterpret_cast<const int64_t *>(w + offsetof(ChunkDesc, pbase)));
+            cd.n = uload_i(reinterpret_cast<const int32_t *>(w + offsetof(ChunkDesc, n)));
+            cd.item0 = uload_i(reinterpret_cast<const int32_t *>(w + offsetof(ChunkDesc, item0)));
+            cd.block0 = uload_i(reinterpret_cast<const int32_t *>(w + offsetof(ChunkDesc, block0)));
         }
         const int n = cd.n;
-        const int r0 = (q - cd.item0) * kWave;
+        const int blk = q - cd.item0 + cd.block0;
+        const int r0 = blk * kWave;
         const Coords<DY, DX> cp(a.base, cd);
 
         // ---- pass 1: lane = reference i, candidates uniform
@@ -348,7 +351,7 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
             term = psi_of_count(nP) - psi_of_count(nTP) - psi_of_count(nPS);
         const double sum = wave_sum(term);
         if (lane == 0)
-            a.partial[q] = sum;
+            a.partial[cd.pbase + blk] = sum;
         if (a.eps_out != nullptr && cd.out >= 0 && valid) {
             a.eps_out[cd.out + i] = eps;
             a.cnt_out[cd.out + i] = nP;
@@ -452,7 +455,7 @@ __global__ void reduce_kernel(const ChunkDesc *__restrict__ chunks, int n_chunks
     const int nb = (cd.n + kWave - 1) / kWave;
     double s = 0.0;
     for (int b = 0; b < nb; ++b)
-        s += partial[cd.item0 + b];
+        s += partial[cd.pbase + b];
     double te = psi_of_count(k - 1) + s / (double)cd.n;
     if (*err != 0)
         te = __builtin_nan("");

@@ -1,0 +1,790 @@
+// te_serve.cpp -- continuous-batching server for TE jobs.
+//
+// Jobs (a te_problem plus host series and permutations) are submitted from any
+// thread.  A server thread admits them in FIFO order while a job slot is free
+// and its footprint (series, permutations, embedded coordinates, tables,
+// partial sums) fits in the caller's device arena; an admitted job's series is
+// copied into the arena and embedded there once, then stays resident.  Work is
+// issued in steps: each step is one persistent search launch per kernel class
+// (d_y, d_x, k) over reference blocks taken from every ready job in admission
+// order, up to a pair budget, so jobs that arrive while others are on the GPU
+// join at the next step.  Two steps per class may be in flight.  When a job's
+// last blocks are scheduled, its reduction, p-values and result copy are queued
+// behind that step on the same stream.  Per-block partial sums are reduced in
+// block order, so a job's estimates do not depend on what it was batched with.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "te.h"
+#include "te_internal.h"
+#include "te_runtime.h"
+
+namespace te {
+
+namespace {
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// First-fit allocator over [0, size) in 256-byte units.
+struct Arena {
+    size_t size = 0;
+    std::map<size_t, size_t> free_;   // offset -> length
+    size_t used = 0, peak = 0;
+    void init(size_t bytes)
+    {
+        size = bytes / 256 * 256;
+        free_.clear();
+        if (size)
+            free_[0] = size;
+    }
+    bool alloc(size_t bytes, size_t *off)
+    {
+        bytes = align_up(std::max<size_t>(bytes, 1), 256);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t roff = it->first + bytes;
+                free_.erase(it);
+                if (rest)
+                    free_[roff] = rest;
+                used += bytes;
+                peak = std::max(peak, used);
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        bytes = align_up(std::max<size_t>(bytes, 1), 256);
+        used -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+enum JobState { QUEUED, SETUP, READY, DONE, FAILED, CANCELLED };
+
+struct Job {
+    uint64_t id = 0;
+    std::unique_ptr<te_plan_s> plan;
+    std::vector<float> hx, hy;
+    std::vector<int32_t> hperm;
+    Batch batch;                       // layout relative to the job's coordinate block
+    size_t footprint = 0, region = 0;  // bytes, arena offset
+    size_t off_x = 0, off_y = 0, off_perm = 0, off_batch = 0;
+    int cls = 0;
+    JobState state = QUEUED;
+    std::vector<int32_t> next_block;   // per chunk (schedule order): next block to schedule
+    size_t next_chunk = 0;             // first chunk with unscheduled blocks
+    bool all_scheduled = false;
+    hipEvent_t ready_ev = nullptr, done_ev = nullptr;
+    void *stage = nullptr;
+    double t_submit = 0, t_done = 0;
+    te_status status = TE_OK;
+    std::string error;
+    std::vector<double> te_orig, te_surr, pv;
+};
+
+struct StepRec {
+    hipEvent_t ev = nullptr;
+    int slot = 0;
+    int cls = 0;
+    std::vector<uint64_t> finishing;   // jobs whose reduction is queued behind this step
+};
+
+// Jobs with the same (d_y, d_x, k) share a search kernel and a stream; each class
+// owns two step-table slots (arena + pinned staging) so two steps can be in flight.
+struct KernelClass {
+    int d_y = 0, d_x = 0, k = 0;
+    hipStream_t stream = nullptr;
+    SearchConfig cfg{};
+    int in_flight = 0;
+    int64_t max_items = 0;
+    size_t table_cap = 0;
+    size_t table_off[2] = {0, 0};
+    void *stage[2] = {nullptr, nullptr};
+    bool slot_busy[2] = {false, false};
+};
+
+}  // namespace
+
+struct Server {
+    char *arena = nullptr;
+    size_t arena_bytes = 0;
+    int max_slots = 0, max_queue = 0;
+    int64_t step_pairs = 0;
+    bool dry = false;
+    bool held = false;   // admission paused (TE_SERVE_HOLD) until te_serve_resume
+    DeviceInfo dev;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    bool stopping = false;
+    std::thread thr;
+    uint64_t next_id = 1;
+    std::deque<Job *> queue;                       // submitted, not admitted (FIFO)
+    std::list<Job *> resident;                     // admitted, in admission order
+    std::map<uint64_t, std::unique_ptr<Job>> jobs; // all live tickets
+    Arena alloc;
+    std::vector<KernelClass> classes;
+    std::deque<StepRec> steps;                     // in flight, issue order
+    hipStream_t setup_stream = nullptr;
+    PinnedPool pool;
+    // stats
+    std::vector<double> lat;
+    double t_first = 0, t_last = 0;
+    int64_t completed = 0, failed = 0, cancelled = 0, n_steps = 0, est_done = 0, peak_slots = 0;
+
+    te_status start();
+    void loop();
+    int class_of(const te_problem &p);
+    bool admit_one(Job *j);
+    void poll_setup();
+    bool issue_step(int ci);
+    void poll_steps();
+    void finish(Job *j);
+    void fail_job(Job *j, te_status st, const char *msg);
+    void release(Job *j);
+};
+
+// Kernel class of a problem, created on first use (-1 if its step tables do not fit).
+int Server::class_of(const te_problem &p)
+{
+    for (size_t i = 0; i < classes.size(); ++i)
+        if (classes[i].d_y == p.d_y && classes[i].d_x == p.d_x && classes[i].k == p.k)
+            return (int)i;
+    KernelClass c;
+    c.d_y = p.d_y;
+    c.d_x = p.d_x;
+    c.k = p.k;
+    if (!dry)
+        c.cfg = default_config(dev, p.d_y, p.d_x, p.k);
+    c.max_items = (int64_t)std::max(1, dev.n_cu) * std::max(1, c.cfg.wg_per_cu) * std::max(1, c.cfg.waves_per_wg) * 8;
+    c.table_cap = align_up(sizeof(ChunkDesc) * (size_t)c.max_items, 16) + sizeof(int32_t) * (size_t)c.max_items + 64;
+    for (int sl = 0; sl < 2; ++sl) {
+        if (!alloc.alloc(c.table_cap, &c.table_off[sl])) {
+            for (int u = 0; u < sl; ++u)
+                alloc.release(c.table_off[u], c.table_cap);
+            return -1;
+        }
+    }
+    if (!dry) {
+        hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking);
+        for (int sl = 0; sl < 2; ++sl)
+            c.stage[sl] = pool.take(c.table_cap);
+    }
+    classes.push_back(c);
+    return (int)classes.size() - 1;
+}
+
+static size_t job_footprint(const Plan &P, Batch *b, size_t *off_x, size_t *off_y, size_t *off_perm,
+                            size_t *off_batch)
+{
+    const size_t ser = sizeof(float) * (size_t)P.p.n_pairs * P.p.n_trials * P.p.n_samples;
+    const size_t perm = sizeof(int32_t) * (size_t)P.p.n_pairs * P.p.n_points * P.p.n_surrogates * P.p.n_trials;
+    size_t o = 0;
+    *off_x = o;
+    o = align_up(o + ser, 256);
+    *off_y = o;
+    o = align_up(o + ser, 256);
+    *off_perm = o;
+    o = align_up(o + std::max<size_t>(perm, 4), 256);
+    *off_batch = o;
+    return o + b->total_bytes;
+}
+
+void Server::fail_job(Job *j, te_status st, const char *msg)
+{
+    j->status = st;
+    j->error = msg;
+    j->state = FAILED;
+}
+
+void Server::release(Job *j)
+{
+    if (j->footprint)
+        alloc.release(j->region, j->footprint);
+    j->footprint = 0;
+    if (j->stage)
+        pool.give(j->stage);
+    j->stage = nullptr;
+    if (j->ready_ev)
+        hipEventDestroy(j->ready_ev);
+    if (j->done_ev)
+        hipEventDestroy(j->done_ev);
+    j->ready_ev = j->done_ev = nullptr;
+    resident.remove(j);
+}
+
+// Copy the series in, upload the job's tables, embed every chunk once.
+bool Server::admit_one(Job *j)
+{
+    size_t off = 0;
+    if (!alloc.alloc(j->footprint, &off))
+        return false;
+    j->region = off;
+    j->state = SETUP;
+    resident.push_back(j);
+    peak_slots = std::max<int64_t>(peak_slots, (int64_t)resident.size());
+    Batch &b = j->batch;
+    j->next_block.assign(b.chunks.size(), 0);
+    j->next_chunk = 0;
+    if (dry) {
+        j->state = READY;
+        return true;
+    }
+    const Plan &P = j->plan->impl;
+    char *reg = arena + off;
+    char *bat = reg + j->off_batch;
+    const size_t ser = sizeof(float) * j->hx.size();
+    hipError_t e = hipMemcpyAsync(reg + j->off_x, j->hx.data(), ser, hipMemcpyHostToDevice, setup_stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(reg + j->off_y, j->hy.data(), ser, hipMemcpyHostToDevice, setup_stream);
+    if (e == hipSuccess && !j->hperm.empty())
+        e = hipMemcpyAsync(reg + j->off_perm, j->hperm.data(), sizeof(int32_t) * j->hperm.size(),
+                           hipMemcpyHostToDevice, setup_stream);
+    // the job's chunk table with arena-absolute coordinate and partial offsets
+    const int64_t fbase = (int64_t)((off + j->off_batch + b.off_coords) / sizeof(float));
+    const int64_t pbase = (int64_t)((off + j->off_batch + b.off_partial) / sizeof(double));
+    std::vector<char> tables(b.host_tables);
+    ChunkDesc *cd = reinterpret_cast<ChunkDesc *>(tables.data() + (b.off_chunks - b.off_tables));
+    for (size_t c = 0; c < b.chunks.size(); ++c) {
+        cd[c].tp += fbase;
+        cd[c].s += fbase;
+        cd[c].pbase += pbase;
+    }
+    j->stage = pool.take(std::max(b.tables_bytes, sizeof(double) * (b.n_results + b.n_groups) + 64));
+    if (!j->stage) {
+        fail_job(j, TE_ERR_NOMEM, "pinned staging allocation failed");
+        return true;
+    }
+    std::memcpy(j->stage, tables.data(), b.tables_bytes);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(bat + b.off_tables, j->stage, b.tables_bytes, hipMemcpyHostToDevice, setup_stream);
+    int32_t *ctr = reinterpret_cast<int32_t *>(bat + b.off_ctr);
+    if (e == hipSuccess)
+        e = launch_fill_i32(ctr, 0, 4, setup_stream);
+    const int32_t *perm = reinterpret_cast<const int32_t *>(reg + j->off_perm);
+    if (e == hipSuccess && !b.perm_rows.empty())
+        e = launch_check_perms(perm, reinterpret_cast<const int64_t *>(bat + b.off_prow),
+                               reinterpret_cast<const int32_t *>(bat + b.off_prc), (int)b.perm_rows.size(), ctr + 1,
+                               setup_stream);
+    if (e == hipSuccess)
+        e = launch_embed(reinterpret_cast<const float *>(reg + j->off_x), reinterpret_cast<const float *>(reg + j->off_y),
+                         perm, reinterpret_cast<const EmbedTask *>(bat + b.off_tasks), (int)b.tasks.size(),
+                         reinterpret_cast<float *>(bat + b.off_coords), P.p.n_trials, P.p.n_samples, P.p.d_y, P.p.d_x,
+                         P.p.tau, P.p.u, ctr + 1, setup_stream);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&j->ready_ev, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipEventRecord(j->ready_ev, setup_stream);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&j->done_ev, hipEventDisableTiming);
+    if (e != hipSuccess)
+        fail_job(j, TE_ERR_DEVICE, hipGetErrorString(e));
+    // the host copies are no longer needed once the upload has been enqueued
+    // (pageable sources are staged by the runtime before hipMemcpyAsync returns)
+    return true;
+}
+
+void Server::poll_setup()
+{
+    for (Job *j : resident)
+        if (j->state == SETUP && hipEventQuery(j->ready_ev) == hipSuccess) {
+            j->state = READY;
+            std::vector<float>().swap(j->hx);
+            std::vector<float>().swap(j->hy);
+            std::vector<int32_t>().swap(j->hperm);
+        }
+}
+
+// One search launch for class ci over blocks of ready jobs, FIFO, up to the pair budget.
+bool Server::issue_step(int ci)
+{
+    KernelClass &kc = classes[ci];
+    std::vector<ChunkDesc> tab;
+    std::vector<int32_t> starts;
+    std::vector<Job *> finishing;
+    int64_t items = 0, pairs = 0;
+    const int64_t max_items = kc.max_items;
+    const int slot = kc.slot_busy[0] ? 1 : 0;
+    if (kc.slot_busy[slot])
+        return false;
+    for (Job *j : resident) {
+        if (j->state != READY || j->cls != ci || j->all_scheduled)
+            continue;
+        Batch &b = j->batch;
+        const int64_t fbase = dry ? 0 : (int64_t)((j->region + j->off_batch + b.off_coords) / sizeof(float));
+        const int64_t pb = dry ? 0 : (int64_t)((j->region + j->off_batch + b.off_partial) / sizeof(double));
+        while (j->next_chunk < b.chunks.size() && pairs < step_pairs && items < max_items) {
+            const size_t c = j->next_chunk;
+            const ChunkDesc &src = b.chunks[c];
+            const int nb = (src.n + kWave - 1) / kWave;
+            const int64_t per_block = (int64_t)kWave * src.n;
+            int64_t want = std::max<int64_t>(1, (step_pairs - pairs) / std::max<int64_t>(per_block, 1));
+            want = std::min<int64_t>(want, max_items - items);
+            const int take = (int)std::min<int64_t>(want, nb - j->next_block[c]);
+            ChunkDesc d = src;
+            d.tp += fbase;
+            d.s += fbase;
+            d.pbase += pb;
+            d.item0 = (int32_t)items;
+            d.block0 = j->next_block[c];
+            tab.push_back(d);
+            starts.push_back((int32_t)items);
+            items += take;
+            pairs += (int64_t)take * per_block;
+            j->next_block[c] += take;
+            if (j->next_block[c] >= nb)
+                j->next_chunk++;
+        }
+        if (j->next_chunk >= b.chunks.size()) {
+            j->all_scheduled = true;
+            finishing.push_back(j);
+        }
+        if (pairs >= step_pairs || items >= max_items)
+            break;
+    }
+    if (tab.empty())
+        return false;
+    StepRec st;
+    st.cls = ci;
+    st.slot = slot;
+    for (Job *j : finishing)
+        st.finishing.push_back(j->id);
+    n_steps++;
+    kc.slot_busy[slot] = true;
+    kc.in_flight++;
+    if (dry) {
+        steps.push_back(st);
+        return true;
+    }
+    // step table into the class's slot
+    const size_t tb = align_up(sizeof(ChunkDesc) * tab.size(), 16) + sizeof(int32_t) * starts.size();
+    char *h = static_cast<char *>(kc.stage[slot]);
+    std::memcpy(h, tab.data(), sizeof(ChunkDesc) * tab.size());
+    std::memcpy(h + align_up(sizeof(ChunkDesc) * tab.size(), 16), starts.data(), sizeof(int32_t) * starts.size());
+    char *dtab = arena + kc.table_off[slot];
+    hipError_t e = hipMemcpyAsync(dtab, h, tb, hipMemcpyHostToDevice, kc.stream);
+    int32_t *ctr = reinterpret_cast<int32_t *>(dtab + align_up(tb, 16));
+    if (e == hipSuccess)
+        e = launch_fill_i32(ctr, 0, 1, kc.stream);
+    SearchArgs a{};
+    a.base = reinterpret_cast<const float *>(arena);
+    a.chunks = reinterpret_cast<const ChunkDesc *>(dtab);
+    a.item_start = reinterpret_cast<const int32_t *>(dtab + align_up(sizeof(ChunkDesc) * tab.size(), 16));
+    a.n_chunks = (int32_t)tab.size();
+    a.n_items = (int32_t)items;
+    a.k = kc.k;
+    a.counter = ctr;
+    a.partial = reinterpret_cast<double *>(arena);
+    const int64_t full = (int64_t)dev.n_cu * kc.cfg.wg_per_cu * kc.cfg.waves_per_wg;
+    if (e == hipSuccess)
+        e = launch_search_timed(a, kc.d_y, kc.d_x, kc.cfg, (int)std::max<int64_t>(1, std::min<int64_t>(full, items)),
+                                kc.stream);
+    // reductions of the jobs this step completes, behind it on the same stream
+    for (Job *j : finishing) {
+        if (e != hipSuccess)
+            break;
+        Batch &b = j->batch;
+        char *bat = arena + j->region + j->off_batch;
+        const ChunkDesc *jc = reinterpret_cast<const ChunkDesc *>(bat + b.off_chunks);
+        const int32_t *jctr = reinterpret_cast<const int32_t *>(bat + b.off_ctr);
+        double *res = reinterpret_cast<double *>(bat + b.off_results);
+        double *pv = reinterpret_cast<double *>(bat + b.off_pv);
+        e = launch_reduce(jc, (int)b.chunks.size(), reinterpret_cast<const double *>(arena), kc.k, jctr + 1, res,
+                          kc.stream);
+        if (e == hipSuccess)
+            e = launch_pvalues(res, b.n_groups, b.n_surr, pv, kc.stream);
+        char *out = static_cast<char *>(j->stage);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(out, res, sizeof(double) * b.n_results, hipMemcpyDeviceToHost, kc.stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(out + sizeof(double) * b.n_results, pv, sizeof(double) * b.n_groups,
+                               hipMemcpyDeviceToHost, kc.stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(out + sizeof(double) * (b.n_results + b.n_groups), jctr + 1, sizeof(int32_t),
+                               hipMemcpyDeviceToHost, kc.stream);
+        if (e == hipSuccess)
+            e = hipEventRecord(j->done_ev, kc.stream);
+    }
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&st.ev, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipEventRecord(st.ev, kc.stream);
+    if (e != hipSuccess) {
+        for (Job *j : finishing)
+            fail_job(j, TE_ERR_DEVICE, hipGetErrorString(e));
+        if (st.ev)
+            hipEventDestroy(st.ev);
+        st.ev = nullptr;
+    }
+    steps.push_back(st);
+    return true;
+}
+
+void Server::finish(Job *j)
+{
+    const Batch &b = j->batch;
+    const te_problem &p = j->plan->impl.p;
+    const int G = p.n_pairs * p.n_points;
+    j->te_orig.assign(G, NAN);
+    j->te_surr.assign((size_t)G * p.n_surrogates, NAN);
+    j->pv.assign(G, NAN);
+    if (!dry && j->state != FAILED) {
+        const char *out = static_cast<const char *>(j->stage);
+        const double *res = reinterpret_cast<const double *>(out);
+        const double *pv = res + b.n_results;
+        int32_t err = 0;
+        std::memcpy(&err, out + sizeof(double) * (b.n_results + b.n_groups), sizeof err);
+        for (int gi = 0; gi < b.n_groups; ++gi) {
+            const int g = b.groups[gi];
+            const double *r = res + (size_t)gi * (b.n_surr + 1);
+            j->te_orig[g] = r[0];
+            for (int s = 0; s < b.n_surr; ++s)
+                j->te_surr[(size_t)g * b.n_surr + s] = r[1 + s];
+            j->pv[g] = pv[gi];
+        }
+        if (err)
+            fail_job(j, TE_ERR_INVALID, "non-finite input value or invalid surrogate permutation");
+    }
+    j->t_done = now_s();
+    if (j->state != FAILED) {
+        j->state = DONE;
+        completed++;
+        est_done += (int64_t)G * (p.n_surrogates + 1);
+        lat.push_back(j->t_done - j->t_submit);
+        t_last = j->t_done;
+    } else {
+        failed++;
+    }
+    release(j);
+}
+
+// Retire every finished step (steps of one class finish in issue order on its stream).
+void Server::poll_steps()
+{
+    for (auto it = steps.begin(); it != steps.end();) {
+        StepRec &st = *it;
+        if (!dry && st.ev && hipEventQuery(st.ev) != hipSuccess) {
+            ++it;
+            continue;
+        }
+        for (uint64_t id : st.finishing) {
+            auto jt = jobs.find(id);
+            if (jt != jobs.end() && jt->second->state != CANCELLED) {
+                Job *j = jt->second.get();
+                // the result copy was recorded before the step's event on the same stream
+                if (!dry && j->done_ev && j->state != FAILED)
+                    hipEventSynchronize(j->done_ev);
+                finish(j);
+            }
+        }
+        if (!dry && st.ev)
+            hipEventDestroy(st.ev);
+        classes[st.cls].in_flight--;
+        classes[st.cls].slot_busy[st.slot] = false;
+        it = steps.erase(it);
+        cv_done.notify_all();
+    }
+}
+
+void Server::loop()
+{
+    std::unique_lock<std::mutex> lk(mu);
+    while (true) {
+        if (stopping && queue.empty() && resident.empty() && steps.empty())
+            break;
+        // admission: FIFO, no overtaking
+        while (!held && !queue.empty() && (int)resident.size() < max_slots) {
+            Job *j = queue.front();
+            if (j->state == CANCELLED) {
+                queue.pop_front();
+                continue;
+            }
+            if (!admit_one(j))
+                break;
+            queue.pop_front();
+            if (j->state == FAILED) {
+                j->t_done = now_s();
+                failed++;
+                release(j);
+                cv_done.notify_all();
+            }
+        }
+        if (!dry)
+            poll_setup();
+        bool issued = false;
+        for (size_t ci = 0; ci < classes.size(); ++ci)
+            if (classes[ci].in_flight < 2)
+                issued |= issue_step((int)ci);
+        poll_steps();
+        const bool busy = !steps.empty() || !queue.empty() ||
+                          std::any_of(resident.begin(), resident.end(), [](Job *j) { return j->state == SETUP; });
+        if (!busy && !issued) {
+            if (stopping && resident.empty() && queue.empty())
+                break;
+            cv_work.wait_for(lk, std::chrono::milliseconds(2));
+        } else if (!issued) {
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(dry ? 0 : 50));
+            lk.lock();
+        }
+    }
+}
+
+te_status Server::start()
+{
+    if (!dry) {
+        te_status st = current_device(&dev);
+        if (st != TE_OK)
+            return st;
+        hipError_t e = hipStreamCreateWithFlags(&setup_stream, hipStreamNonBlocking);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipStreamCreate");
+    } else {
+        dev.n_cu = 256;
+    }
+    alloc.init(arena_bytes);
+    thr = std::thread([this] { loop(); });
+    return TE_OK;
+}
+
+}  // namespace te
+
+struct te_server_s {
+    te::Server impl;
+};
+
+using namespace te;
+
+extern "C" {
+
+te_status te_serve_open(void *arena, size_t arena_bytes, int32_t max_slots, int32_t max_queue, int64_t step_pairs,
+                        int32_t flags, te_server *out)
+{
+    clear_error();
+    if (!out)
+        return fail(TE_ERR_INVALID, "null argument");
+    *out = nullptr;
+    const bool dry = (flags & TE_SERVE_DRY_RUN) != 0;
+    if ((!arena && !dry) || arena_bytes < 4096 || max_slots < 1 || max_queue < 1)
+        return fail(TE_ERR_INVALID, "need an arena of >= 4096 bytes, max_slots >= 1 and max_queue >= 1");
+    auto s = std::make_unique<te_server_s>();
+    Server &S = s->impl;
+    S.arena = static_cast<char *>(arena);
+    S.arena_bytes = arena_bytes;
+    S.max_slots = max_slots;
+    S.max_queue = max_queue;
+    S.step_pairs = step_pairs > 0 ? step_pairs : (int64_t)4000000000LL;
+    S.dry = dry;
+    S.held = (flags & TE_SERVE_HOLD) != 0;
+    te_status st = S.start();
+    if (st != TE_OK)
+        return st;
+    *out = s.release();
+    return TE_OK;
+}
+
+te_status te_serve_submit(te_server srv, const te_problem *problem, const float *x, const float *y,
+                          const int32_t *perms, uint64_t *ticket)
+{
+    clear_error();
+    if (!srv || !problem || !x || !y || !ticket)
+        return fail(TE_ERR_INVALID, "null argument");
+    Server &S = srv->impl;
+    auto j = std::make_unique<Job>();
+    te_plan pl = nullptr;
+    te_status st = te_plan_create(problem, &pl);
+    if (st != TE_OK)
+        return st;
+    j->plan.reset(pl);
+    const Plan &P = pl->impl;
+    if (P.p.n_surrogates > 0 && !perms)
+        return fail(TE_ERR_INVALID, "n_surrogates > 0 needs perms");
+    j->batch = P.full;
+    j->footprint = job_footprint(P, &j->batch, &j->off_x, &j->off_y, &j->off_perm, &j->off_batch);
+    if (j->footprint > S.alloc.size)
+        return fail(TE_ERR_NOMEM, "job needs %zu bytes, the arena holds %zu", j->footprint, S.alloc.size);
+    const size_t ns = (size_t)P.p.n_pairs * P.p.n_trials * P.p.n_samples;
+    j->hx.assign(x, x + ns);
+    j->hy.assign(y, y + ns);
+    if (P.p.n_surrogates > 0) {
+        const size_t np = (size_t)P.p.n_pairs * P.p.n_points * P.p.n_surrogates * P.p.n_trials;
+        j->hperm.assign(perms, perms + np);
+    }
+    std::lock_guard<std::mutex> lk(S.mu);
+    if (S.stopping)
+        return fail(TE_ERR_CANCELLED, "server is closing");
+    if ((int)S.queue.size() >= S.max_queue)
+        return fail(TE_ERR_BUSY, "queue full (%d)", S.max_queue);
+    j->id = S.next_id++;
+    j->t_submit = now_s();
+    if (S.t_first == 0)
+        S.t_first = j->t_submit;
+    j->cls = S.class_of(P.p);
+    if (j->cls < 0)
+        return fail(TE_ERR_NOMEM, "the arena cannot hold the step tables of a new kernel class");
+    if (j->footprint > S.alloc.size)
+        return fail(TE_ERR_NOMEM, "job needs %zu bytes, the arena holds %zu", j->footprint, S.alloc.size);
+    *ticket = j->id;
+    S.queue.push_back(j.get());
+    S.jobs[j->id] = std::move(j);
+    S.cv_work.notify_all();
+    return TE_OK;
+}
+
+te_status te_serve_wait(te_server srv, uint64_t ticket, int64_t timeout_us, double *te_orig, double *te_surr,
+                        double *p_value)
+{
+    clear_error();
+    if (!srv)
+        return fail(TE_ERR_INVALID, "null server");
+    Server &S = srv->impl;
+    std::unique_lock<std::mutex> lk(S.mu);
+    auto it = S.jobs.find(ticket);
+    if (it == S.jobs.end())
+        return fail(TE_ERR_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+    Job *j = it->second.get();
+    auto terminal = [&] { return j->state == DONE || j->state == FAILED || j->state == CANCELLED; };
+    if (timeout_us < 0)
+        S.cv_done.wait(lk, terminal);
+    else if (!S.cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), terminal))
+        return fail(TE_ERR_TIMEOUT, "ticket %llu not finished", (unsigned long long)ticket);
+    te_status st = TE_OK;
+    if (j->state == DONE) {
+        if (te_orig)
+            std::copy(j->te_orig.begin(), j->te_orig.end(), te_orig);
+        if (te_surr)
+            std::copy(j->te_surr.begin(), j->te_surr.end(), te_surr);
+        if (p_value)
+            std::copy(j->pv.begin(), j->pv.end(), p_value);
+    } else if (j->state == CANCELLED) {
+        st = fail(TE_ERR_CANCELLED, "ticket %llu was cancelled", (unsigned long long)ticket);
+    } else {
+        st = fail(j->status, "%s", j->error.c_str());
+    }
+    S.jobs.erase(it);
+    return st;
+}
+
+te_status te_serve_cancel(te_server srv, uint64_t ticket)
+{
+    clear_error();
+    if (!srv)
+        return fail(TE_ERR_INVALID, "null server");
+    Server &S = srv->impl;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.jobs.find(ticket);
+    if (it == S.jobs.end())
+        return fail(TE_ERR_INVALID, "unknown ticket");
+    Job *j = it->second.get();
+    if (j->state != QUEUED)
+        return fail(TE_ERR_BUSY, "ticket %llu is already admitted", (unsigned long long)ticket);
+    j->state = CANCELLED;
+    S.queue.erase(std::remove(S.queue.begin(), S.queue.end(), j), S.queue.end());
+    S.cancelled++;
+    S.cv_done.notify_all();
+    return TE_OK;
+}
+
+te_status te_serve_resume(te_server srv)
+{
+    clear_error();
+    if (!srv)
+        return fail(TE_ERR_INVALID, "null server");
+    Server &S = srv->impl;
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.held = false;
+    S.cv_work.notify_all();
+    return TE_OK;
+}
+
+te_status te_serve_stats(te_server srv, te_serve_stats_t *out)
+{
+    clear_error();
+    if (!srv || !out)
+        return fail(TE_ERR_INVALID, "null argument");
+    Server &S = srv->impl;
+    std::lock_guard<std::mutex> lk(S.mu);
+    std::vector<double> l = S.lat;
+    std::sort(l.begin(), l.end());
+    auto q = [&](double f) {
+        if (l.empty())
+            return (double)NAN;
+        const size_t i = std::min(l.size() - 1, (size_t)std::ceil(f * l.size()) - (f * l.size() >= 1 ? 1 : 0));
+        return l[i];
+    };
+    out->p50_s = q(0.50);
+    out->p99_s = q(0.99);
+    out->est_per_s = (S.t_last > S.t_first) ? (double)S.est_done / (S.t_last - S.t_first) : 0.0;
+    out->completed = S.completed;
+    out->failed = S.failed;
+    out->cancelled = S.cancelled;
+    out->steps = S.n_steps;
+    out->queued = (int64_t)S.queue.size();
+    out->resident = (int64_t)S.resident.size();
+    out->peak_slots = S.peak_slots;
+    out->peak_bytes = (int64_t)S.alloc.peak;
+    return TE_OK;
+}
+
+te_status te_serve_close(te_server srv)
+{
+    if (!srv)
+        return TE_OK;
+    Server &S = srv->impl;
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        S.stopping = true;
+        for (Job *j : S.queue) {
+            j->state = CANCELLED;
+            S.cancelled++;
+        }
+        S.queue.clear();
+        S.cv_work.notify_all();
+        S.cv_done.notify_all();
+    }
+    if (S.thr.joinable())
+        S.thr.join();
+    for (auto &c : S.classes)
+        if (c.stream)
+            hipStreamDestroy(c.stream);
+    if (S.setup_stream)
+        hipStreamDestroy(S.setup_stream);
+    delete srv;
+    return TE_OK;
+}
+
+}  // extern "C"

@@ -67,66 +67,64 @@ def host_threads() -> int:
 
 
 def cpu_baseline(wl, budget_s: float = 12.0):
-    """Oracle TE for as many windows as fit in about budget_s seconds on the host cores."""
+    """The oracle on the host cores on a bounded, seeded sample of the workload's chunks.
+
+    Chunks are taken in a seeded random order, a batch of one chunk per thread at a
+    time, until about budget_s seconds have passed.  The rate is scaled by directed
+    pairs (the oracle's work grows as N^2): estimates/s = sample pairs/s divided by
+    the workload's mean pairs per estimate."""
     from oracle import oracle
+    from synth.rng import derive_key, permutation
     threads = host_threads()
     jobs, _ = oracle.workload_jobs(wl)
+    order = permutation(derive_key(4068, len(jobs)), len(jobs))
+    jobs = [jobs[i] for i in order]
     done = 0
+    pairs = 0
     t_total = 0.0
-    batch = threads
     while done < len(jobs) and t_total < budget_s:
-        sel = jobs[done:done + batch]
+        sel = jobs[done:done + threads]
         t0 = time.perf_counter()
         oracle.te_jobs(wl.x, wl.y, wl.d_y, wl.d_x, wl.tau, wl.u, wl.k, sel, wl.perms, n_threads=threads)
         t_total += time.perf_counter() - t0
         done += len(sel)
-    return dict(value=done / t_total, unit="estimates/s", cores=threads, kind="oracle",
-                sample="%d of %d windows (N = %d each), %.1f s wall on %d threads"
-                % (done, len(jobs), int(wl.chunk_sizes()[0]), t_total, threads))
+        pairs += sum(j[3] * j[2] * (j[3] * j[2] - 1) for j in sel)
+    mean_pairs = wl.directed_pairs() / wl.n_estimates()
+    return dict(value=(pairs / t_total) / mean_pairs, unit="estimates/s", cores=threads, kind="oracle",
+                sample="%d of %d chunks (seeded random order; %.3g directed pairs), %.1f s wall on %d threads; "
+                       "scaled by directed pairs" % (done, len(jobs), pairs, t_total, threads))
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--plain-steps", type=int, default=3)
-    ap.add_argument("--graph", action="store_true", help="replay the batched step as a hipGraph")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
-                    help="only run a plain device-to-device copy of BYTES, 5 times (HBM counter calibration)")
-    args = ap.parse_args()
-    if args.copy_calibration:
-        import torch
-        a = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(5):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps(dict(copy_bytes=args.copy_calibration, launches=5)))
-        return
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (chunks shard independently "
-              "across GPUs by design; run one process per GPU).", file=sys.stderr)
-        sys.exit(2)
+def make_workload(name):
+    import synth
+    if name == "nonlinear":
+        return synth.nonlinear_ensemble(), "nonlinear_ar_ensemble"
+    if name == "linear":
+        return synth.linear_pair(), "linear_ar_single_estimate"
+    if name == "uneven":
+        return synth.uneven_surrogates(), "uneven_chunks_200_surrogates"
+    if name == "meg":
+        return synth.meg_like(), "meg_like_16_pairs_100_surrogates"
+    raise SystemExit("unknown workload " + name)
 
+
+def batched_record(args, wl, wname):
     import torch
     import paper_1401_4068_amd as te
-    import synth
 
-    torch.cuda.set_device(0)
-    wl = synth.nonlinear_ensemble()
     D = wl.dim
     n = wl.chunk_sizes()
-    pairs_per_pass = int(np.sum(n * (n - 1)))                 # directed pairs, one pass
+    pairs_per_pass = int(wl.directed_pairs())                 # Σ over all chunks of N(N-1)
     x = torch.from_numpy(wl.x).cuda()
     y = torch.from_numpy(wl.y).cuda()
+    perms = torch.from_numpy(wl.perms).cuda() if wl.n_surrogates else None
     plan = te.Plan.from_workload(wl)
+    full, minimum, plain_bytes = plan.workspace_bytes()
     ws = plan.workspace()
     stream = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
 
     def step():
-        return plan.surrogates(x, y, ws=ws, stream=stream, use_graph=args.graph)
+        return plan.surrogates(x, y, perms, ws=ws, stream=stream, use_graph=args.graph)
 
     for _ in range(args.warmup):
         step()
@@ -147,39 +145,53 @@ def main():
     value = est * args.steps / dt
     evals_per_s = 2 * pairs_per_pass * args.steps / dt
 
-    # dominant kernel: the persistent search launch (one per step)
+    # dominant kernel: the persistent search launch (one per step when the workspace holds the batch)
     roof = None
     if k_n > 0:
         avg_s = k_ms / k_n / 1e3
-        ops = pairs_per_pass * ops_per_pair(D)
+        ops = pairs_per_pass * ops_per_pair(D) * args.steps / k_n
         achieved = ops / avg_s / 1e12
         roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_OPS, unit="TFLOP/s",
-                    frac=round(achieved / PEAK_FP32_OPS, 4), traffic=kernel_traffic(),
-                    kernel="search_kernel<3,3,k=4,slots=8>", avg_launch_ms=round(avg_s * 1e3, 4),
-                    launches=k_n, ops_per_launch=ops,
+                    frac=round(achieved / PEAK_FP32_OPS, 4),
+                    traffic=kernel_traffic() if wname == "nonlinear_ar_ensemble" else None,
+                    kernel="search_kernel<%d,%d,k=%d,slots=8>" % (wl.d_y, wl.d_x, wl.k),
+                    avg_launch_ms=round(avg_s * 1e3, 4), launches=k_n, ops_per_launch=int(ops),
                     frac_of_headline_157_3=round(achieved / PEAK_FP32_HEADLINE, 4))
 
-    # plain per-window path on the same workload
+    # plain per-time-point path on the same workload
     plain_rec = None
     if args.plain_steps > 0:
-        plan.estimate(x, y, ws=ws)
+        if wl.n_surrogates == 0:
+            run_plain = lambda: plan.estimate(x, y, ws=ws)                          # noqa: E731
+            label = "te_estimate, one window at a time"
+        else:
+            ws_min = torch.empty(minimum, dtype=torch.uint8, device="cuda")
+            run_plain = lambda: plan.surrogates(x, y, perms, ws=ws_min)              # noqa: E731
+            label = "te_surrogates with the minimum workspace: one window's S+1 chunks per launch"
+        run_plain()
         torch.cuda.synchronize()
         p0 = time.perf_counter()
         for _ in range(args.plain_steps):
-            plain = plan.estimate(x, y, ws=ws)
+            plain = run_plain()
         torch.cuda.synchronize()
         pdt = time.perf_counter() - p0
-        assert np.array_equal(plain, out[0]), "plain and batched paths disagree"
+        ref = out[0] if wl.n_surrogates == 0 else out
+        if wl.n_surrogates == 0:
+            assert np.array_equal(plain, ref), "plain and batched paths disagree"
+        else:
+            for u, v in zip(plain, ref):
+                assert np.array_equal(u, v), "plain and batched paths disagree"
         plain_rec = dict(value=round(est * args.plain_steps / pdt, 2), unit="estimates/s",
-                         ms_per_step=round(pdt / args.plain_steps * 1e3, 3), path="te_estimate, one window at a time")
+                         ms_per_step=round(pdt / args.plain_steps * 1e3, 3), path=label)
 
     rec = dict(
         metric=METRIC, value=round(value, 2), unit="estimates/s", n_gpus=1, steps=args.steps,
         warmup=args.warmup, ms_per_step=round(dt / args.steps * 1e3, 4), higher_is_better=True,
         scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
-        config=dict(workload="nonlinear_ar_ensemble", trials=wl.n_trials, samples=wl.n_samples,
-                    windows=wl.n_points, window_len=int(wl.window_len[0]), points_per_window=int(n[0]),
-                    d_y=wl.d_y, d_x=wl.d_x, tau=wl.tau, u=wl.u, dim=D, k=wl.k, surrogates=0,
+        config=dict(workload=wname, pairs=wl.n_pairs, trials=wl.n_trials, samples=wl.n_samples,
+                    windows=wl.n_points, points_per_window_min=int(n.min()), points_per_window_max=int(n.max()),
+                    d_y=wl.d_y, d_x=wl.d_x, tau=wl.tau, u=wl.u, dim=D, k=wl.k, surrogates=wl.n_surrogates,
+                    estimates_per_step=est, workspace_bytes=int(full),
                     path="batched (te_surrogates, one persistent search launch)" + (", hipGraph" if args.graph else "")),
         distance_evals_per_s=round(evals_per_s, 1),
         pct_fp32_valu_peak=None if roof is None else round(100 * roof["frac"], 2),
@@ -189,6 +201,127 @@ def main():
     )
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl)
+    return rec
+
+
+def served_record(args):
+    """Poisson-arriving jobs through te_serve_* (continuous batching) and the same trace
+    through te_surrogates one job at a time (FIFO)."""
+    import threading
+
+    import torch
+    import paper_1401_4068_amd as te
+    import synth
+
+    def replay(jobs, rate_label):
+        wls = [synth.job_workload(j) for j in jobs]
+        warm_srv = te.Server(arena_bytes=64 << 20, max_slots=4)      # module load, first launches
+        for d in (2, 3, 4):
+            warm = synth.job_workload(dict(id=-d, t=0.0, d=d, W=10, R=30, S=2, seed=d))
+            warm_srv.wait(warm_srv.submit(warm), timeout_s=120)
+        warm_srv.close()
+        srv = te.Server(arena_bytes=args.arena_gb << 30, max_slots=args.slots, step_pairs=args.step_pairs)
+        tickets = [None] * len(jobs)
+        t_sub = [0.0] * len(jobs)
+        t0 = time.perf_counter() + 0.01
+
+        def submitter():
+            for i, (j, wl) in enumerate(zip(jobs, wls)):
+                d = t0 + j["t"] - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                t_sub[i] = time.perf_counter()
+                tickets[i] = srv.submit(wl)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        for i in range(len(jobs)):
+            srv.wait(tickets[i], timeout_s=3600)
+        st = srv.stats()
+        t_end = time.perf_counter()
+        served_est_per_s = sum(1 + j["S"] for j in jobs) / (t_end - t_sub[0])
+        srv.close()
+        est = sum((1 + j["S"]) for j in jobs)
+        pairs = sum((1 + j["S"]) * (j["R"] * j["W"]) * (j["R"] * j["W"] - 1) for j in jobs)
+        # FIFO through the batched path, one job at a time (arrival-ordered, queueing included)
+        done = 0.0
+        fifo_lat = []
+        for j, wl in zip(jobs, wls):
+            plan = te.Plan.from_workload(wl)
+            x = torch.from_numpy(wl.x).cuda()
+            y = torch.from_numpy(wl.y).cuda()
+            perms = torch.from_numpy(wl.perms).cuda() if wl.n_surrogates else None
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            plan.surrogates(x, y, perms)
+            svc = time.perf_counter() - s0
+            start = max(j["t"], done)
+            done = start + svc
+            fifo_lat.append(done - j["t"])
+            plan.close()
+        fifo_span = done - jobs[0]["t"]
+        return dict(rate_per_s=rate_label, jobs=len(jobs), estimates=est, directed_pairs=int(pairs),
+                    served=dict(p50_s=st["p50_s"], p99_s=st["p99_s"], est_per_s=served_est_per_s,
+                                span_s=t_end - t_sub[0], steps=st["steps"], peak_slots=st["peak_slots"],
+                                peak_arena_bytes=st["peak_bytes"]),
+                    fifo=dict(p50_s=float(np.percentile(fifo_lat, 50)), p99_s=float(np.percentile(fifo_lat, 99)),
+                              est_per_s=est / fifo_span, span_s=fifo_span))
+
+    trace = synth.served_jobs(n_jobs=args.jobs, rate=200.0)
+    r1 = replay(trace, 200.0)
+    # second trace: arrival rate rescaled to 0.8 x the measured served capacity (jobs/s)
+    cap_jobs = r1["jobs"] / r1["served"]["span_s"]
+    rate2 = 0.8 * cap_jobs
+    trace2 = synth.served_jobs(n_jobs=args.jobs, rate=rate2, seed_offset=1)
+    r2 = replay(trace2, round(rate2, 3))
+    rec = dict(metric=METRIC, value=round(r1["served"]["est_per_s"], 2), unit="estimates/s", n_gpus=1,
+               steps=1, warmup=1, ms_per_step=round(r1["served"]["span_s"] * 1e3, 1), higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+               config=dict(workload="served_mix", arrivals="poisson", jobs=args.jobs, dims=[5, 7, 9],
+                           points_per_job="log-uniform 1000..100000", surrogates="0..500", k=4,
+                           arena_gb=args.arena_gb, max_slots=args.slots, step_pairs=args.step_pairs),
+               latency_s=dict(p50=r1["served"]["p50_s"], p99=r1["served"]["p99_s"]),
+               traces=[r1, r2])
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="nonlinear", choices=["nonlinear", "linear", "uneven", "meg", "served"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--graph", action="store_true", help="replay the batched step as a hipGraph")
+    ap.add_argument("--jobs", type=int, default=60, help="served workload: jobs per trace")
+    ap.add_argument("--arena-gb", type=int, default=32, help="served workload: device arena")
+    ap.add_argument("--slots", type=int, default=64, help="served workload: resident job slots")
+    ap.add_argument("--step-pairs", type=int, default=0, help="served workload: pairs per search launch")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES, 5 times (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_bytes=args.copy_calibration, launches=5)))
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (chunks shard independently "
+              "across GPUs by design; run one process per GPU).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    if args.workload == "served":
+        rec = served_record(args)
+    else:
+        wl, wname = make_workload(args.workload)
+        rec = batched_record(args, wl, wname)
     print(json.dumps(rec), flush=True)
 
 

@@ -338,6 +338,9 @@ bool Server::issue_step(int ci)
     std::vector<Job *> finishing;
     int64_t items = 0, pairs = 0;
     const int64_t max_items = kc.max_items;
+    // a step always fills the GPU (one work item per resident wave); the pair budget
+    // only bounds it beyond that, so large-N jobs do not starve the launch
+    const int64_t min_items = max_items / 8;
     const int slot = kc.slot_busy[0] ? 1 : 0;
     if (kc.slot_busy[slot])
         return false;
@@ -347,12 +350,13 @@ bool Server::issue_step(int ci)
         Batch &b = j->batch;
         const int64_t fbase = dry ? 0 : (int64_t)((j->region + j->off_batch + b.off_coords) / sizeof(float));
         const int64_t pb = dry ? 0 : (int64_t)((j->region + j->off_batch + b.off_partial) / sizeof(double));
-        while (j->next_chunk < b.chunks.size() && pairs < step_pairs && items < max_items) {
+        while (j->next_chunk < b.chunks.size() && (pairs < step_pairs || items < min_items) && items < max_items) {
             const size_t c = j->next_chunk;
             const ChunkDesc &src = b.chunks[c];
             const int nb = (src.n + kWave - 1) / kWave;
             const int64_t per_block = (int64_t)kWave * src.n;
             int64_t want = std::max<int64_t>(1, (step_pairs - pairs) / std::max<int64_t>(per_block, 1));
+            want = std::max<int64_t>(want, min_items - items);
             want = std::min<int64_t>(want, max_items - items);
             const int take = (int)std::min<int64_t>(want, nb - j->next_block[c]);
             ChunkDesc d = src;
@@ -373,7 +377,7 @@ bool Server::issue_step(int ci)
             j->all_scheduled = true;
             finishing.push_back(j);
         }
-        if (pairs >= step_pairs || items >= max_items)
+        if ((pairs >= step_pairs && items >= min_items) || items >= max_items)
             break;
     }
     if (tab.empty())

@@ -205,6 +205,24 @@ te_status te_serve_stats(te_server srv, te_serve_stats_t *out);
  * thread and free the server.  The arena may be freed afterwards. */
 te_status te_serve_close(te_server srv);
 
+/* ------------------------------------------------------------------ tuning
+ * The search kernel's launch shape -- candidate slots per lane in the counting
+ * pass (4, 8 or 16), waves per workgroup (1, 2 or 4) and resident workgroups per
+ * compute unit -- is chosen per (d_y, d_x, k, chunk-size bucket floor(log2 N)).
+ * te_autotune times every shape on n_chunks synthetic chunks of n_points points
+ * (uniform random coordinates generated in ws) and records the fastest in a
+ * process-wide table that plans and servers created afterwards use (the nearest
+ * bucket within 2).  ws must hold n_chunks*n_points*(1+d_y+d_x) floats plus
+ * small tables (TE_ERR_NOMEM names the size).  Outputs may be NULL.
+ * te_tune_save / te_tune_load write / read the table as text; the environment
+ * variable TE_TUNE_FILE names a table loaded on first use. */
+te_status te_autotune(int32_t d_y, int32_t d_x, int32_t k, int32_t n_points, int32_t n_chunks,
+                      void *ws, size_t ws_bytes, void *hip_stream,
+                      int32_t *slots, int32_t *waves_per_wg, int32_t *wg_per_cu, double *best_ms);
+te_status te_tune_save(const char *path);
+te_status te_tune_load(const char *path);
+te_status te_tune_clear(void);
+
 /* Measurement hook.  While enabled, every search-kernel launch made by
  * te_estimate, te_surrogates and te_knn_counts outside graph capture is
  * bracketed by HIP events recorded on the launch stream.  te_profile_read

@@ -5,6 +5,8 @@ in include/te.h).  This package only marshals arguments; PyTorch supplies
 device memory and streams.
 """
 from ._lib import LIB_PATH, TEError, lib
-from .api import Plan, Server, knn_counts, profile_enable, profile_read, version
+from .api import (Plan, Server, autotune, knn_counts, profile_enable, profile_read, tune_clear, tune_load, tune_save,
+                  version)
 
-__all__ = ["LIB_PATH", "Plan", "Server", "TEError", "knn_counts", "lib", "profile_enable", "profile_read", "version"]
+__all__ = ["LIB_PATH", "Plan", "Server", "TEError", "autotune", "knn_counts", "lib", "profile_enable", "profile_read",
+           "tune_clear", "tune_load", "tune_save", "version"]

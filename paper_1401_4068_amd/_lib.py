@@ -68,6 +68,11 @@ SIGNATURES = {
     "te_serve_cancel": ([_vp, ctypes.c_uint64], _st),
     "te_serve_stats": ([_vp, ctypes.POINTER(ServeStats)], _st),
     "te_serve_close": ([_vp], _st),
+    "te_autotune": ([_i32, _i32, _i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                     ctypes.POINTER(_i32), _dp], _st),
+    "te_tune_save": ([ctypes.c_char_p], _st),
+    "te_tune_load": ([ctypes.c_char_p], _st),
+    "te_tune_clear": ([], _st),
     "te_knn_counts": ([_vp, _i64, ctypes.POINTER(_i64), _i32, _i32, _i32, _i32, _vp, _sz, _vp, _vp, _vp, _dp], _st),
 }
 

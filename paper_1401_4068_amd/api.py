@@ -264,6 +264,36 @@ def knn_counts(pts, offsets, d_y, d_x, k, stream=None, ws=None, want_te=True):
     return eps[:total], cnt[:, :total], te
 
 
+def autotune(d_y, d_x, k, n_points, n_chunks=None, stream=None):
+    """Time every search launch shape on synthetic chunks (te_autotune); the winner is
+    used by plans created afterwards.  Returns the chosen shape and its time."""
+    torch = _torch()
+    if n_chunks is None:
+        n_chunks = max(1, int(4096 * 64 // max(n_points, 1)))       # about one GPU-full of work items
+    D = 1 + d_y + d_x
+    need = 4 * n_points * n_chunks * D + 64 * n_chunks + 8 * (n_points // 64 + 2) * n_chunks + (1 << 16)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    sl, wpg, wg = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    ms = ctypes.c_double()
+    sh, _ = _stream_handle(stream)
+    check(lib().te_autotune(d_y, d_x, k, n_points, n_chunks, ctypes.c_void_p(ws.data_ptr()), need, sh,
+                            ctypes.byref(sl), ctypes.byref(wpg), ctypes.byref(wg), ctypes.byref(ms)))
+    return dict(slots=sl.value, waves_per_wg=wpg.value, wg_per_cu=wg.value, ms=ms.value, n_points=n_points,
+                n_chunks=n_chunks)
+
+
+def tune_save(path):
+    check(lib().te_tune_save(str(path).encode()))
+
+
+def tune_load(path):
+    check(lib().te_tune_load(str(path).encode()))
+
+
+def tune_clear():
+    check(lib().te_tune_clear())
+
+
 def profile_enable(on: bool = True):
     """Bracket search-kernel launches with HIP events (te_profile_enable)."""
     check(lib().te_profile_enable(int(bool(on))))

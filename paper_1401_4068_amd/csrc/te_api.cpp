@@ -251,7 +251,9 @@ te_status Plan::ensure_device() const
     te_status st = current_device(&dev);
     if (st != TE_OK)
         return st;
-    cfg = default_config(dev, p.d_y, p.d_x, p.k);
+    std::vector<int64_t> ns(npts);
+    std::nth_element(ns.begin(), ns.begin() + ns.size() / 2, ns.end());
+    cfg = default_config(dev, p.d_y, p.d_x, p.k, ns[ns.size() / 2]);
     dev_ready = true;
     return TE_OK;
 }

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <mutex>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -24,18 +25,33 @@ static int env_int(const char *name, int dflt)
     return (v && *v) ? std::atoi(v) : dflt;
 }
 
-// Launch shape of the search kernel.  TE_SLOTS and TE_WG_PER_CU override the
-// defaults (used by the tuner and for measurements).
-SearchConfig default_config(const DeviceInfo &dev, int d_y, int d_x, int k)
+bool tuned_config(int d_y, int d_x, int k, int64_t n, SearchConfig *out);
+
+// Launch shape of the search kernel for chunks of about n points: the autotuner's
+// table entry when there is one (TE_TUNE_FILE names a table loaded on first use),
+// else 8 slots, 4 waves per workgroup and full occupancy.  TE_SLOTS,
+// TE_WAVES_PER_WG and TE_WG_PER_CU override single fields (measurements).
+SearchConfig default_config(const DeviceInfo &dev, int d_y, int d_x, int k, int64_t n)
 {
     (void)dev;
-    SearchConfig c;
-    c.slots = env_int("TE_SLOTS", 8);
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const char *f = std::getenv("TE_TUNE_FILE");
+        if (f && *f)
+            te_tune_load(f);
+    });
+    SearchConfig c{8, 4, 0};
+    SearchConfig t;
+    if (tuned_config(d_y, d_x, k, n, &t))
+        c = t;
+    c.slots = env_int("TE_SLOTS", c.slots);
     if (c.slots != 4 && c.slots != 8 && c.slots != 16)
         c.slots = 8;
-    c.waves_per_wg = 4;
+    c.waves_per_wg = std::min(kMaxWavesPerWG, std::max(1, env_int("TE_WAVES_PER_WG", c.waves_per_wg)));
     const int occ = search_occupancy(d_y, d_x, k, c.slots, c.waves_per_wg);
-    c.wg_per_cu = std::max(1, env_int("TE_WG_PER_CU", occ));
+    if (c.wg_per_cu <= 0 || c.wg_per_cu > std::max(1, occ))
+        c.wg_per_cu = std::max(1, occ);
+    c.wg_per_cu = std::max(1, env_int("TE_WG_PER_CU", c.wg_per_cu));
     return c;
 }
 
@@ -358,7 +374,7 @@ te_status te_knn_counts(const float *pts, int64_t dim_stride, const int64_t *off
     te_status s = current_device(&dev);
     if (s != TE_OK)
         return s;
-    SearchConfig cfg = default_config(dev, d_y, d_x, k);
+    SearchConfig cfg = default_config(dev, d_y, d_x, k, total / n_chunks);
     char *ws = static_cast<char *>(ws_);
     size_t o = 0;
     const size_t off_chunks = o;

@@ -363,6 +363,20 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
 
 // ------------------------------------------------------------ small kernels
 
+// Uniform [0, 1) floats from a counter hash (SplitMix64 finaliser); synthetic
+// data for launch-shape tuning only.
+__global__ void fill_uniform_kernel(float *p, int64_t n, uint64_t seed)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    p[i] = (float)(z >> 40) * (1.0f / 16777216.0f);
+}
+
 __global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -540,6 +554,14 @@ hipError_t launch_search(const SearchArgs &a, int d_y, int d_x, const SearchConf
     const int wpg = cfg.waves_per_wg;
     const int blocks = (grid_waves + wpg - 1) / wpg;
     hipLaunchKernelGGL(f, dim3(blocks), dim3(kWave * wpg), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_uniform(float *p, int64_t n, uint64_t seed, hipStream_t st)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(fill_uniform_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, seed);
     return hipGetLastError();
 }
 

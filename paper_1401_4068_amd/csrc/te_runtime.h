@@ -17,8 +17,9 @@ te_status fail(te_status st, const char *fmt, ...);
 te_status hip_fail(hipError_t e, const char *what);
 void clear_error();
 te_status current_device(DeviceInfo *out);
-SearchConfig default_config(const DeviceInfo &dev, int d_y, int d_x, int k);
+SearchConfig default_config(const DeviceInfo &dev, int d_y, int d_x, int k, int64_t n);
 size_t align_up(size_t v, size_t a);
+int size_bucket(int64_t n);
 
 // A set of chunks laid out in one device workspace, with the host copy of its
 // tables.  Chunks are stored in schedule (longest-first) order.

@@ -98,8 +98,8 @@ enum JobState { QUEUED, SETUP, READY, DONE, FAILED, CANCELLED };
 struct Job {
     uint64_t id = 0;
     std::unique_ptr<te_plan_s> plan;
-    std::vector<float> hx, hy;
-    std::vector<int32_t> hperm;
+    void *hin = nullptr;               // pinned copy of x | y | perms, taken at submit
+    size_t hin_bytes = 0, hin_y = 0, hin_perm = 0, n_series = 0, n_perm = 0;
     Batch batch;                       // layout relative to the job's coordinate block
     size_t footprint = 0, region = 0;  // bytes, arena offset
     size_t off_x = 0, off_y = 0, off_perm = 0, off_batch = 0;
@@ -127,7 +127,8 @@ struct StepRec {
 // owns two step-table slots (arena + pinned staging) so two steps can be in flight.
 struct KernelClass {
     int d_y = 0, d_x = 0, k = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream[2] = {nullptr, nullptr};   // steps alternate, so one step's tail overlaps the next
+    hipEvent_t last_ev[2] = {nullptr, nullptr};   // completion of the last step issued on each stream
     SearchConfig cfg{};
     int in_flight = 0;
     int64_t max_items = 0;
@@ -189,7 +190,7 @@ int Server::class_of(const te_problem &p)
     c.d_x = p.d_x;
     c.k = p.k;
     if (!dry)
-        c.cfg = default_config(dev, p.d_y, p.d_x, p.k);
+        c.cfg = default_config(dev, p.d_y, p.d_x, p.k, 16384);
     c.max_items = (int64_t)std::max(1, dev.n_cu) * std::max(1, c.cfg.wg_per_cu) * std::max(1, c.cfg.waves_per_wg) * 8;
     c.table_cap = align_up(sizeof(ChunkDesc) * (size_t)c.max_items, 16) + sizeof(int32_t) * (size_t)c.max_items + 64;
     for (int sl = 0; sl < 2; ++sl) {
@@ -200,9 +201,11 @@ int Server::class_of(const te_problem &p)
         }
     }
     if (!dry) {
-        hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking);
-        for (int sl = 0; sl < 2; ++sl)
+        for (int sl = 0; sl < 2; ++sl) {
+            hipStreamCreateWithFlags(&c.stream[sl], hipStreamNonBlocking);
+            hipEventCreateWithFlags(&c.last_ev[sl], hipEventDisableTiming);
             c.stage[sl] = pool.take(c.table_cap);
+        }
     }
     classes.push_back(c);
     return (int)classes.size() - 1;
@@ -239,6 +242,12 @@ void Server::release(Job *j)
     if (j->stage)
         pool.give(j->stage);
     j->stage = nullptr;
+    if (j->hin) {
+        if (!dry && j->ready_ev)
+            hipEventSynchronize(j->ready_ev);   // uploads read the pinned inputs
+        pool.give(j->hin);
+    }
+    j->hin = nullptr;
     if (j->ready_ev)
         hipEventDestroy(j->ready_ev);
     if (j->done_ev)
@@ -267,13 +276,14 @@ bool Server::admit_one(Job *j)
     const Plan &P = j->plan->impl;
     char *reg = arena + off;
     char *bat = reg + j->off_batch;
-    const size_t ser = sizeof(float) * j->hx.size();
-    hipError_t e = hipMemcpyAsync(reg + j->off_x, j->hx.data(), ser, hipMemcpyHostToDevice, setup_stream);
+    const size_t ser = sizeof(float) * j->n_series;
+    const char *hin = static_cast<const char *>(j->hin);
+    hipError_t e = hipMemcpyAsync(reg + j->off_x, hin, ser, hipMemcpyHostToDevice, setup_stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(reg + j->off_y, j->hy.data(), ser, hipMemcpyHostToDevice, setup_stream);
-    if (e == hipSuccess && !j->hperm.empty())
-        e = hipMemcpyAsync(reg + j->off_perm, j->hperm.data(), sizeof(int32_t) * j->hperm.size(),
-                           hipMemcpyHostToDevice, setup_stream);
+        e = hipMemcpyAsync(reg + j->off_y, hin + j->hin_y, ser, hipMemcpyHostToDevice, setup_stream);
+    if (e == hipSuccess && j->n_perm)
+        e = hipMemcpyAsync(reg + j->off_perm, hin + j->hin_perm, sizeof(int32_t) * j->n_perm, hipMemcpyHostToDevice,
+                           setup_stream);
     // the job's chunk table with arena-absolute coordinate and partial offsets
     const int64_t fbase = (int64_t)((off + j->off_batch + b.off_coords) / sizeof(float));
     const int64_t pbase = (int64_t)((off + j->off_batch + b.off_partial) / sizeof(double));
@@ -313,8 +323,6 @@ bool Server::admit_one(Job *j)
         e = hipEventCreateWithFlags(&j->done_ev, hipEventDisableTiming);
     if (e != hipSuccess)
         fail_job(j, TE_ERR_DEVICE, hipGetErrorString(e));
-    // the host copies are no longer needed once the upload has been enqueued
-    // (pageable sources are staged by the runtime before hipMemcpyAsync returns)
     return true;
 }
 
@@ -323,9 +331,9 @@ void Server::poll_setup()
     for (Job *j : resident)
         if (j->state == SETUP && hipEventQuery(j->ready_ev) == hipSuccess) {
             j->state = READY;
-            std::vector<float>().swap(j->hx);
-            std::vector<float>().swap(j->hy);
-            std::vector<int32_t>().swap(j->hperm);
+            if (j->hin)
+                pool.give(j->hin);      // inputs are on the device now
+            j->hin = nullptr;
         }
 }
 
@@ -400,10 +408,11 @@ bool Server::issue_step(int ci)
     std::memcpy(h, tab.data(), sizeof(ChunkDesc) * tab.size());
     std::memcpy(h + align_up(sizeof(ChunkDesc) * tab.size(), 16), starts.data(), sizeof(int32_t) * starts.size());
     char *dtab = arena + kc.table_off[slot];
-    hipError_t e = hipMemcpyAsync(dtab, h, tb, hipMemcpyHostToDevice, kc.stream);
+    hipStream_t sm = kc.stream[slot];
+    hipError_t e = hipMemcpyAsync(dtab, h, tb, hipMemcpyHostToDevice, sm);
     int32_t *ctr = reinterpret_cast<int32_t *>(dtab + align_up(tb, 16));
     if (e == hipSuccess)
-        e = launch_fill_i32(ctr, 0, 1, kc.stream);
+        e = launch_fill_i32(ctr, 0, 1, sm);
     SearchArgs a{};
     a.base = reinterpret_cast<const float *>(arena);
     a.chunks = reinterpret_cast<const ChunkDesc *>(dtab);
@@ -416,8 +425,11 @@ bool Server::issue_step(int ci)
     const int64_t full = (int64_t)dev.n_cu * kc.cfg.wg_per_cu * kc.cfg.waves_per_wg;
     if (e == hipSuccess)
         e = launch_search_timed(a, kc.d_y, kc.d_x, kc.cfg, (int)std::max<int64_t>(1, std::min<int64_t>(full, items)),
-                                kc.stream);
-    // reductions of the jobs this step completes, behind it on the same stream
+                                sm);
+    // reductions of the jobs this step completes, behind it on the same stream; a job's
+    // earlier blocks may sit in the previous step on the other stream, so wait for it first
+    if (e == hipSuccess && !finishing.empty())
+        e = hipStreamWaitEvent(sm, kc.last_ev[1 - slot], 0);
     for (Job *j : finishing) {
         if (e != hipSuccess)
             break;
@@ -428,25 +440,27 @@ bool Server::issue_step(int ci)
         double *res = reinterpret_cast<double *>(bat + b.off_results);
         double *pv = reinterpret_cast<double *>(bat + b.off_pv);
         e = launch_reduce(jc, (int)b.chunks.size(), reinterpret_cast<const double *>(arena), kc.k, jctr + 1, res,
-                          kc.stream);
+                          sm);
         if (e == hipSuccess)
-            e = launch_pvalues(res, b.n_groups, b.n_surr, pv, kc.stream);
+            e = launch_pvalues(res, b.n_groups, b.n_surr, pv, sm);
         char *out = static_cast<char *>(j->stage);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(out, res, sizeof(double) * b.n_results, hipMemcpyDeviceToHost, kc.stream);
+            e = hipMemcpyAsync(out, res, sizeof(double) * b.n_results, hipMemcpyDeviceToHost, sm);
         if (e == hipSuccess)
             e = hipMemcpyAsync(out + sizeof(double) * b.n_results, pv, sizeof(double) * b.n_groups,
-                               hipMemcpyDeviceToHost, kc.stream);
+                               hipMemcpyDeviceToHost, sm);
         if (e == hipSuccess)
             e = hipMemcpyAsync(out + sizeof(double) * (b.n_results + b.n_groups), jctr + 1, sizeof(int32_t),
-                               hipMemcpyDeviceToHost, kc.stream);
+                               hipMemcpyDeviceToHost, sm);
         if (e == hipSuccess)
-            e = hipEventRecord(j->done_ev, kc.stream);
+            e = hipEventRecord(j->done_ev, sm);
     }
     if (e == hipSuccess)
         e = hipEventCreateWithFlags(&st.ev, hipEventDisableTiming);
     if (e == hipSuccess)
-        e = hipEventRecord(st.ev, kc.stream);
+        e = hipEventRecord(st.ev, sm);
+    if (e == hipSuccess)
+        e = hipEventRecord(kc.last_ev[slot], sm);
     if (e != hipSuccess) {
         for (Job *j : finishing)
             fail_job(j, TE_ERR_DEVICE, hipGetErrorString(e));
@@ -641,27 +655,41 @@ te_status te_serve_submit(te_server srv, const te_problem *problem, const float 
     j->footprint = job_footprint(P, &j->batch, &j->off_x, &j->off_y, &j->off_perm, &j->off_batch);
     if (j->footprint > S.alloc.size)
         return fail(TE_ERR_NOMEM, "job needs %zu bytes, the arena holds %zu", j->footprint, S.alloc.size);
-    const size_t ns = (size_t)P.p.n_pairs * P.p.n_trials * P.p.n_samples;
-    j->hx.assign(x, x + ns);
-    j->hy.assign(y, y + ns);
-    if (P.p.n_surrogates > 0) {
-        const size_t np = (size_t)P.p.n_pairs * P.p.n_points * P.p.n_surrogates * P.p.n_trials;
-        j->hperm.assign(perms, perms + np);
+    // stage the inputs in pinned memory now, on the submitting thread, so the
+    // server's uploads are asynchronous copies
+    j->n_series = (size_t)P.p.n_pairs * P.p.n_trials * P.p.n_samples;
+    j->n_perm = P.p.n_surrogates > 0 ? (size_t)P.p.n_pairs * P.p.n_points * P.p.n_surrogates * P.p.n_trials : 0;
+    j->hin_y = align_up(sizeof(float) * j->n_series, 256);
+    j->hin_perm = j->hin_y + align_up(sizeof(float) * j->n_series, 256);
+    j->hin_bytes = j->hin_perm + sizeof(int32_t) * j->n_perm;
+    if (!S.dry) {
+        j->hin = S.pool.take(j->hin_bytes);
+        if (!j->hin)
+            return fail(TE_ERR_NOMEM, "pinned staging allocation failed");
+        char *h = static_cast<char *>(j->hin);
+        std::memcpy(h, x, sizeof(float) * j->n_series);
+        std::memcpy(h + j->hin_y, y, sizeof(float) * j->n_series);
+        if (j->n_perm)
+            std::memcpy(h + j->hin_perm, perms, sizeof(int32_t) * j->n_perm);
     }
     std::lock_guard<std::mutex> lk(S.mu);
+    auto reject = [&](te_status st2, const char *msg) {
+        if (j->hin)
+            S.pool.give(j->hin);
+        j->hin = nullptr;
+        return fail(st2, "%s", msg);
+    };
     if (S.stopping)
-        return fail(TE_ERR_CANCELLED, "server is closing");
+        return reject(TE_ERR_CANCELLED, "server is closing");
     if ((int)S.queue.size() >= S.max_queue)
-        return fail(TE_ERR_BUSY, "queue full (%d)", S.max_queue);
+        return reject(TE_ERR_BUSY, "queue full");
     j->id = S.next_id++;
     j->t_submit = now_s();
     if (S.t_first == 0)
         S.t_first = j->t_submit;
     j->cls = S.class_of(P.p);
     if (j->cls < 0)
-        return fail(TE_ERR_NOMEM, "the arena cannot hold the step tables of a new kernel class");
-    if (j->footprint > S.alloc.size)
-        return fail(TE_ERR_NOMEM, "job needs %zu bytes, the arena holds %zu", j->footprint, S.alloc.size);
+        return reject(TE_ERR_NOMEM, "the arena cannot hold the step tables of a new kernel class");
     *ticket = j->id;
     S.queue.push_back(j.get());
     S.jobs[j->id] = std::move(j);
@@ -783,8 +811,12 @@ te_status te_serve_close(te_server srv)
     if (S.thr.joinable())
         S.thr.join();
     for (auto &c : S.classes)
-        if (c.stream)
-            hipStreamDestroy(c.stream);
+        for (int sl = 0; sl < 2; ++sl) {
+            if (c.stream[sl])
+                hipStreamDestroy(c.stream[sl]);
+            if (c.last_ev[sl])
+                hipEventDestroy(c.last_ev[sl]);
+        }
     if (S.setup_stream)
         hipStreamDestroy(S.setup_stream);
     delete srv;

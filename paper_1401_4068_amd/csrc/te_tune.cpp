@@ -1,0 +1,257 @@
+// te_tune.cpp -- autotuner for the search kernel's launch shape.
+//
+// A shape is (candidate slots per lane in the counting pass, waves per
+// workgroup, resident workgroups per CU).  te_autotune times every shape on
+// synthetic chunks of the requested (d_y, d_x, k, N) generated on the device,
+// keeps the fastest in a process-wide table keyed by (d_y, d_x, k, N bucket),
+// and default_config() consults that table.  te_tune_save / te_tune_load keep
+// the table in a text file ("d_y d_x k n_bucket slots waves wg_per_cu ms" per line).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "te.h"
+#include "te_internal.h"
+#include "te_runtime.h"
+
+namespace te {
+
+int search_occupancy(int d_y, int d_x, int k, int slots, int waves_per_wg);
+hipError_t launch_fill_uniform(float *p, int64_t n, uint64_t seed, hipStream_t st);
+
+namespace {
+
+struct TuneKey {
+    int d_y, d_x, k, bucket;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(d_y, d_x, k, bucket) < std::tie(o.d_y, o.d_x, o.k, o.bucket);
+    }
+};
+
+struct TuneVal {
+    SearchConfig cfg;
+    double ms;
+};
+
+std::mutex g_mu;
+std::map<TuneKey, TuneVal> g_table;
+
+}  // namespace
+
+// Chunk-size bucket: floor(log2(N)), so 1000..1023 -> 9, 5000 -> 12, 50000 -> 15.
+int size_bucket(int64_t n)
+{
+    int b = 0;
+    while (n > 1) {
+        n >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+bool tuned_config(int d_y, int d_x, int k, int64_t n, SearchConfig *out)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_table.empty())
+        return false;
+    const int b = size_bucket(n);
+    const TuneVal *best = nullptr;
+    int bestd = 1 << 30;
+    for (auto &kv : g_table) {
+        const TuneKey &key = kv.first;
+        if (key.d_y != d_y || key.d_x != d_x || key.k != k)
+            continue;
+        const int d = std::abs(key.bucket - b);
+        if (d < bestd) {
+            bestd = d;
+            best = &kv.second;
+        }
+    }
+    if (!best || bestd > 2)
+        return false;
+    *out = best->cfg;
+    return true;
+}
+
+}  // namespace te
+
+using namespace te;
+
+extern "C" {
+
+te_status te_autotune(int32_t d_y, int32_t d_x, int32_t k, int32_t n_points, int32_t n_chunks, void *ws_,
+                      size_t ws_bytes, void *hip_stream, int32_t *slots, int32_t *waves_per_wg,
+                      int32_t *wg_per_cu, double *best_ms)
+{
+    clear_error();
+    if (d_y < 1 || d_y > kMaxDimY || d_x < 1 || d_x > kMaxDimX || k < 1 || k > kMaxK || n_points <= k ||
+        n_chunks < 1 || !ws_)
+        return fail(TE_ERR_INVALID, "bad tuning problem");
+    const int D = 1 + d_y + d_x;
+    const int64_t total = (int64_t)n_points * n_chunks;
+    const int64_t items = (int64_t)n_chunks * ((n_points + kWave - 1) / kWave);
+    size_t o = 0;
+    const size_t off_pts = o;
+    o = align_up(o + sizeof(float) * (size_t)total * D, 256);
+    const size_t off_chunks = o;
+    o = align_up(o + sizeof(ChunkDesc) * n_chunks, 256);
+    const size_t off_items = o;
+    o = align_up(o + sizeof(int32_t) * n_chunks, 256);
+    const size_t off_partial = o;
+    o = align_up(o + sizeof(double) * (size_t)items, 256);
+    const size_t off_ctr = o;
+    o += 256;
+    if (ws_bytes < o)
+        return fail(TE_ERR_NOMEM, "tuning workspace needs %zu bytes", o);
+    DeviceInfo dev;
+    te_status s = current_device(&dev);
+    if (s != TE_OK)
+        return s;
+    char *ws = static_cast<char *>(ws_);
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::vector<ChunkDesc> cd(n_chunks);
+    std::vector<int32_t> starts(n_chunks);
+    for (int c = 0; c < n_chunks; ++c) {
+        ChunkDesc d{};
+        d.tp = (int64_t)c * n_points;
+        d.s = (int64_t)c * n_points + (int64_t)(1 + d_y) * total;
+        d.ld = total;
+        d.out = -1;
+        d.n = n_points;
+        d.item0 = (int32_t)((int64_t)c * ((n_points + kWave - 1) / kWave));
+        d.pbase = d.item0;
+        d.block0 = 0;
+        d.result = c;
+        cd[c] = d;
+        starts[c] = d.item0;
+    }
+    hipError_t e = hipMemcpy(ws + off_chunks, cd.data(), sizeof(ChunkDesc) * n_chunks, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(ws + off_items, starts.data(), sizeof(int32_t) * n_chunks, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = launch_fill_uniform(reinterpret_cast<float *>(ws + off_pts), total * D, 0x7e5eed, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "tuning setup");
+    SearchArgs a{};
+    a.base = reinterpret_cast<const float *>(ws + off_pts);
+    a.chunks = reinterpret_cast<const ChunkDesc *>(ws + off_chunks);
+    a.item_start = reinterpret_cast<const int32_t *>(ws + off_items);
+    a.n_chunks = n_chunks;
+    a.n_items = (int32_t)items;
+    a.k = k;
+    a.counter = reinterpret_cast<int32_t *>(ws + off_ctr);
+    a.partial = reinterpret_cast<double *>(ws + off_partial);
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    SearchConfig best{};
+    double best_t = 1e30;
+    const int slot_set[] = {4, 8, 16};
+    const int wpg_set[] = {1, 2, 4};
+    for (int sl : slot_set)
+        for (int wpg : wpg_set) {
+            const int occ = search_occupancy(d_y, d_x, k, sl, wpg);
+            if (occ < 1)
+                continue;
+            std::vector<int> wgs = {occ};
+            if (occ >= 2)
+                wgs.push_back(occ / 2);
+            for (int wg : wgs) {
+                SearchConfig c{sl, wpg, wg};
+                double tmin = 1e30;
+                for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+                    e = launch_fill_i32(a.counter, 0, 1, st);
+                    if (e == hipSuccess)
+                        e = hipEventRecord(e0, st);
+                    const int64_t full = (int64_t)dev.n_cu * wg * wpg;
+                    if (e == hipSuccess)
+                        e = launch_search(a, d_y, d_x, c, (int)std::max<int64_t>(1, std::min<int64_t>(full, items)), st);
+                    if (e == hipSuccess)
+                        e = hipEventRecord(e1, st);
+                    if (e == hipSuccess)
+                        e = hipEventSynchronize(e1);
+                    float ms = 0;
+                    if (e == hipSuccess)
+                        hipEventElapsedTime(&ms, e0, e1);
+                    tmin = std::min(tmin, (double)ms);
+                }
+                if (e != hipSuccess)
+                    break;
+                if (tmin < best_t) {
+                    best_t = tmin;
+                    best = c;
+                }
+            }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess)
+        return hip_fail(e, "tuning run");
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_table[TuneKey{d_y, d_x, k, size_bucket(n_points)}] = TuneVal{best, best_t};
+    }
+    if (slots)
+        *slots = best.slots;
+    if (waves_per_wg)
+        *waves_per_wg = best.waves_per_wg;
+    if (wg_per_cu)
+        *wg_per_cu = best.wg_per_cu;
+    if (best_ms)
+        *best_ms = best_t;
+    return TE_OK;
+}
+
+te_status te_tune_save(const char *path)
+{
+    clear_error();
+    FILE *f = path ? std::fopen(path, "w") : nullptr;
+    if (!f)
+        return fail(TE_ERR_INVALID, "cannot write %s", path ? path : "(null)");
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &kv : g_table)
+        std::fprintf(f, "%d %d %d %d %d %d %d %.6f\n", kv.first.d_y, kv.first.d_x, kv.first.k, kv.first.bucket,
+                     kv.second.cfg.slots, kv.second.cfg.waves_per_wg, kv.second.cfg.wg_per_cu, kv.second.ms);
+    std::fclose(f);
+    return TE_OK;
+}
+
+te_status te_tune_load(const char *path)
+{
+    clear_error();
+    FILE *f = path ? std::fopen(path, "r") : nullptr;
+    if (!f)
+        return fail(TE_ERR_INVALID, "cannot read %s", path ? path : "(null)");
+    int a, b, c, d, sl, w, g;
+    double ms;
+    int n = 0;
+    std::lock_guard<std::mutex> lk(g_mu);
+    while (std::fscanf(f, "%d %d %d %d %d %d %d %lf", &a, &b, &c, &d, &sl, &w, &g, &ms) == 8) {
+        if (a < 1 || a > kMaxDimY || b < 1 || b > kMaxDimX || c < 1 || c > kMaxK || !search_supported(a, b, c, sl) ||
+            w < 1 || w > kMaxWavesPerWG || g < 1)
+            continue;
+        g_table[TuneKey{a, b, c, d}] = TuneVal{SearchConfig{sl, w, g}, ms};
+        ++n;
+    }
+    std::fclose(f);
+    return n > 0 ? TE_OK : fail(TE_ERR_INVALID, "no tuning entries in %s", path);
+}
+
+te_status te_tune_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table.clear();
+    return TE_OK;
+}
+
+}  // extern "C"

@@ -259,3 +259,35 @@ def test_invalid_permutation_is_rejected(te):
     x, y, perms = dev(wl)
     with pytest.raises(te.TEError):
         plan.surrogates(x, y, perms)
+
+
+@pytest.mark.parametrize("slots,wpg,wg", [(4, 1, 3), (16, 2, 1), (8, 1, 7), (16, 4, 0)])
+def test_results_do_not_depend_on_launch_shape(te, monkeypatch, slots, wpg, wg):
+    wl = synth.uneven_surrogates(R=150, T=60, n_points=3, n_surrogates=3, n_lo=300, n_hi=3000)
+    x, y, perms = dev(wl)
+    ref = te.Plan.from_workload(wl).surrogates(x, y, perms)
+    monkeypatch.setenv("TE_SLOTS", str(slots))
+    monkeypatch.setenv("TE_WAVES_PER_WG", str(wpg))
+    if wg:
+        monkeypatch.setenv("TE_WG_PER_CU", str(wg))
+    say("shape", slots, wpg, wg)
+    got = te.Plan.from_workload(wl).surrogates(x, y, perms)
+    for u, v in zip(ref, got):
+        np.testing.assert_array_equal(u, v)
+
+
+def test_autotune_records_a_valid_shape(te, tmp_path):
+    r = te.autotune(3, 3, 4, 2000, n_chunks=40)
+    say("tuned", r)
+    assert r["slots"] in (4, 8, 16) and 1 <= r["waves_per_wg"] <= 4 and r["wg_per_cu"] >= 1 and r["ms"] > 0
+    path = tmp_path / "tune.txt"
+    te.tune_save(path)
+    row = path.read_text().split()
+    assert row[:7] == ["3", "3", "4", "10", str(r["slots"]), str(r["waves_per_wg"]), str(r["wg_per_cu"])]
+    # a plan created now uses the tuned shape; its estimates are unchanged
+    wl = synth.generic((31,), R=100, T=40, d_y=3, d_x=3, starts=(20,), windows=(20,))
+    x, y, _ = dev(wl)
+    a = te.Plan.from_workload(wl).estimate(x, y)
+    te.tune_clear()
+    b = te.Plan.from_workload(wl).estimate(x, y)
+    np.testing.assert_array_equal(a, b)

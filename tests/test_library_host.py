@@ -84,3 +84,22 @@ def test_history_rule_matches_embedding():
     from paper_1401_4068_amd import TEError
     with pytest.raises(TEError):
         _plan(d_y=4, d_x=4, tau=2, u=5, window_start=[10])
+
+
+def test_tuning_table_roundtrip(tmp_path):
+    import paper_1401_4068_amd as te
+    _lib_or_build()
+    src = tmp_path / "tune.txt"
+    src.write_text("3 3 4 12 16 2 3 1.5\n2 2 4 11 4 1 6 0.25\n9 9 4 11 4 1 6 0.25\n3 3 4 13 5 2 3 1.0\n")
+    te.tune_clear()
+    te.tune_load(src)                                 # invalid rows (d = 9, slots = 5) are skipped
+    out = tmp_path / "out.txt"
+    te.tune_save(out)
+    rows = sorted(out.read_text().split("\n"))
+    rows = [r for r in rows if r]
+    assert [r.split()[:7] for r in rows] == [["2", "2", "4", "11", "4", "1", "6"], ["3", "3", "4", "12", "16", "2", "3"]]
+    te.tune_clear()
+    empty = tmp_path / "empty.txt"
+    empty.write_text("garbage\n")
+    with pytest.raises(te.TEError):
+        te.tune_load(empty)

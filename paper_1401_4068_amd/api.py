@@ -271,7 +271,9 @@ def autotune(d_y, d_x, k, n_points, n_chunks=None, stream=None):
     if n_chunks is None:
         n_chunks = max(1, int(4096 * 64 // max(n_points, 1)))       # about one GPU-full of work items
     D = 1 + d_y + d_x
-    need = 4 * n_points * n_chunks * D + 64 * n_chunks + 8 * (n_points // 64 + 2) * n_chunks + (1 << 16)
+    npad = 1 << max(0, (n_points - 1).bit_length())
+    need = (8 * n_points * n_chunks * D + 4 * n_points * n_chunks + 8 * npad * n_chunks + 160 * n_chunks
+            + 8 * (n_points // 64 + 2) * n_chunks + (1 << 20))
     ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     sl, wpg, wg = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     ms = ctypes.c_double()

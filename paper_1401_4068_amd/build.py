@@ -23,8 +23,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + INCLUDE, "-I" + CSRC]
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
     cmd = ["hipcc", "--offload-arch=" + ARCH] + COMMON + DEVICE_FLAGS + ["-c", src, "-o", obj]
-    if src.endswith(".cpp"):
-        cmd = ["hipcc"] + COMMON + ["-c", src, "-o", obj]
+
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -119,6 +120,8 @@ void Batch::finish_layout()
     o = align_up(o + sizeof(int64_t) * perm_rows.size(), 16);
     off_prc = o;
     o = align_up(o + sizeof(int32_t) * perm_rc.size(), 16);
+    off_sorts = o;
+    o = align_up(o + sizeof(SortTask) * sorts.size(), 16);
     tables_bytes = o - off_tables;
     off_partial = align_up(o, 256);
     o = off_partial + sizeof(double) * (size_t)std::max<int64_t>(n_items, 1);
@@ -128,6 +131,10 @@ void Batch::finish_layout()
     o = off_pv + sizeof(double) * (size_t)std::max(n_groups, 1);
     off_ctr = align_up(o, 256);
     o = off_ctr + sizeof(int32_t) * 4;
+    off_sigma = align_up(o, 256);
+    o = off_sigma + sizeof(int32_t) * (size_t)n_sigma;
+    off_scratch = align_up(o, 256);
+    o = off_scratch + sizeof(uint64_t) * (size_t)n_scratch;
     total_bytes = align_up(o, 256);
 
     host_tables.assign(tables_bytes, 0);
@@ -141,6 +148,23 @@ void Batch::finish_layout()
                     sizeof(int64_t) * perm_rows.size());
         std::memcpy(host_tables.data() + (off_prc - off_tables), perm_rc.data(), sizeof(int32_t) * perm_rc.size());
     }
+    if (!sorts.empty())
+        std::memcpy(host_tables.data() + (off_sorts - off_tables), sorts.data(), sizeof(SortTask) * sorts.size());
+}
+
+bool sorting_enabled()
+{
+    const char *v = std::getenv("TE_NO_SORT");
+    return !(v && *v && *v != '0');
+}
+
+// Padded sort length: the next power of two >= n.
+int sort_npad(int n)
+{
+    int p = 1;
+    while (p < n)
+        p <<= 1;
+    return p;
 }
 
 // ------------------------------------------------------------------- plan
@@ -166,12 +190,34 @@ te_status Plan::build_group_batch(const std::vector<int> &groups, int n_surr, Ba
         const int N = (int)npts[c];
         const int64_t tp = fl;
         fl += (int64_t)dT * N;
+        int64_t sig = -1;
+        if (sorted) {
+            SortTask st{};
+            sig = b->n_sigma;
+            st.sig = sig;
+            st.npad = sort_npad(N);
+            st.scratch = -1;
+            if (st.npad > kSortLds) {
+                st.scratch = b->n_scratch;
+                b->n_scratch += st.npad;
+            }
+            st.key_off = -1;
+            st.mode = 0;
+            st.pair = pair;
+            st.w = wstart[c];
+            st.W = wlen[c];
+            st.Rc = trials[c];
+            st.n = N;
+            b->sorts.push_back(st);
+            b->n_sigma += N;
+        }
         for (int s = 0; s <= n_surr; ++s) {
             ChunkDesc d{};
             d.tp = tp;
             d.s = fl;
             d.ld = N;
             d.out = -1;
+            d.perm = -1;
             d.n = N;
             d.result = gi * (n_surr + 1) + s;
             b->chunks.push_back(d);
@@ -179,6 +225,7 @@ te_status Plan::build_group_batch(const std::vector<int> &groups, int n_surr, Ba
             t.tp = s == 0 ? tp : -1;
             t.s = fl;
             t.perm = -1;
+            t.sig = sig;
             if (s > 0) {
                 t.perm = (((int64_t)pair * p.n_points + c) * n_surr + (s - 1)) * p.n_trials;
                 b->perm_rows.push_back(t.perm);
@@ -287,8 +334,13 @@ te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, co
         if (e != hipSuccess)
             return hip_fail(e, "check_perms launch");
     }
-    e = launch_embed(x, y, perms, reinterpret_cast<const EmbedTask *>(ws + b.off_tasks), (int)b.tasks.size(), base,
-                     p.n_trials, p.n_samples, p.d_y, p.d_x, p.tau, p.u, ctr + 1, st);
+    int32_t *sigma = reinterpret_cast<int32_t *>(ws + b.off_sigma);
+    e = launch_sort(y, nullptr, reinterpret_cast<const SortTask *>(ws + b.off_sorts), (int)b.sorts.size(), sigma,
+                    reinterpret_cast<uint64_t *>(ws + b.off_scratch), p.n_trials, p.n_samples, st);
+    if (e != hipSuccess)
+        return hip_fail(e, "sort launch");
+    e = launch_embed(x, y, perms, sigma, reinterpret_cast<const EmbedTask *>(ws + b.off_tasks), (int)b.tasks.size(),
+                     base, p.n_trials, p.n_samples, p.d_y, p.d_x, p.tau, p.u, ctr + 1, st);
     if (e != hipSuccess)
         return hip_fail(e, "embed launch");
     SearchArgs a{};
@@ -303,6 +355,7 @@ te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, co
     a.eps_out = nullptr;
     a.cnt_out = nullptr;
     a.cnt_stride = 0;
+    a.sorted = sorted ? 1 : 0;
     if ((e = launch_search_timed(a, p.d_y, p.d_x, cfg, grid_waves(b.n_items), st)) != hipSuccess)
         return hip_fail(e, "search launch");
     double *res = reinterpret_cast<double *>(ws + b.off_results);
@@ -387,6 +440,7 @@ te_status te_plan_create(const te_problem *pr, te_plan *out)
     auto plan = std::make_unique<te_plan_s>();
     Plan &P = plan->impl;
     P.p = p;
+    P.sorted = sorting_enabled();
     const int h = history(p);
     for (int c = 0; c < p.n_points; ++c) {
         const int w = p.window_start[c];
@@ -434,7 +488,9 @@ te_status te_plan_create(const te_problem *pr, te_plan *out)
                     align_up(sizeof(double) * (size_t)((maxn + kWave - 1) / kWave), 256) +
                     align_up(sizeof(double) * (size_t)p.n_pairs * p.n_points, 256) +
                     align_up(sizeof(int32_t) * 4 * (size_t)p.n_pairs * p.n_points + 16, 256) +
-                    align_up((sizeof(ChunkDesc) + sizeof(EmbedTask) + 16) * (size_t)p.n_pairs * p.n_points, 256) +
+                    align_up((sizeof(ChunkDesc) + sizeof(EmbedTask) + sizeof(SortTask) + 16) * (size_t)p.n_pairs *
+                                 p.n_points, 256) +
+                    align_up(sizeof(int32_t) * (size_t)maxn, 256) + sizeof(uint64_t) * (size_t)sort_npad((int)maxn) +
                     4096;
     *out = plan.release();
     return TE_OK;

@@ -219,7 +219,15 @@ te_status Plan::estimate_plain(const float *x, const float *y, char *ws, size_t 
     const size_t tbl_chunks = 0;
     const size_t tbl_items = align_up(sizeof(ChunkDesc) * G, 16);
     const size_t tbl_tasks = tbl_items + align_up(sizeof(int32_t) * G, 16);
-    const size_t tbl_bytes = tbl_tasks + sizeof(EmbedTask) * G;
+    const size_t tbl_sorts = tbl_tasks + align_up(sizeof(EmbedTask) * G, 16);
+    const size_t tbl_bytes = tbl_sorts + sizeof(SortTask) * G;
+    o = align_up(o + tbl_bytes, 256);
+    const size_t off_sigma = o;                       // one window's map, reused window after window
+    o = align_up(o + sizeof(int32_t) * (size_t)maxn, 256);
+    const size_t off_scratch = o;
+    o = align_up(o + sizeof(uint64_t) * (size_t)sort_npad((int)maxn), 256);
+    if (o > ws_bytes)
+        return fail(TE_ERR_NOMEM, "plain-path layout needs %zu bytes, workspace has %zu", o, ws_bytes);
 
     const size_t out_off = align_up(tbl_bytes, 256);
     char *stg = static_cast<char *>(pool.take(out_off + sizeof(double) * G + sizeof(int32_t) * 4 * G));
@@ -228,6 +236,7 @@ te_status Plan::estimate_plain(const float *x, const float *y, char *ws, size_t 
     ChunkDesc *hc = reinterpret_cast<ChunkDesc *>(stg + tbl_chunks);
     int32_t *hi = reinterpret_cast<int32_t *>(stg + tbl_items);
     EmbedTask *ht = reinterpret_cast<EmbedTask *>(stg + tbl_tasks);
+    SortTask *hs = reinterpret_cast<SortTask *>(stg + tbl_sorts);
     const int dT = 1 + p.d_y;
     for (int g = 0; g < G; ++g) {
         const int pair = g / p.n_points, c = g % p.n_points;
@@ -237,6 +246,7 @@ te_status Plan::estimate_plain(const float *x, const float *y, char *ws, size_t 
         d.s = (int64_t)dT * N;
         d.ld = N;
         d.out = -1;
+        d.perm = -1;
         d.n = N;
         d.item0 = 0;
         d.block0 = 0;
@@ -244,10 +254,23 @@ te_status Plan::estimate_plain(const float *x, const float *y, char *ws, size_t 
         d.result = g;
         hc[g] = d;
         hi[g] = 0;
+        SortTask so{};
+        so.sig = 0;
+        so.npad = sort_npad(N);
+        so.scratch = so.npad > kSortLds ? 0 : -1;
+        so.key_off = -1;
+        so.mode = 0;
+        so.pair = pair;
+        so.w = wstart[c];
+        so.W = wlen[c];
+        so.Rc = trials[c];
+        so.n = N;
+        hs[g] = so;
         EmbedTask t{};
         t.tp = 0;
         t.s = (int64_t)dT * N;
         t.perm = -1;
+        t.sig = sorted ? 0 : -1;
         t.pair = pair;
         t.w = wstart[c];
         t.W = wlen[c];
@@ -265,10 +288,18 @@ te_status Plan::estimate_plain(const float *x, const float *y, char *ws, size_t 
     const ChunkDesc *dc = reinterpret_cast<const ChunkDesc *>(ws + off_tables + tbl_chunks);
     const int32_t *di = reinterpret_cast<const int32_t *>(ws + off_tables + tbl_items);
     const EmbedTask *dt = reinterpret_cast<const EmbedTask *>(ws + off_tables + tbl_tasks);
+    const SortTask *ds = reinterpret_cast<const SortTask *>(ws + off_tables + tbl_sorts);
+    int32_t *sigma = reinterpret_cast<int32_t *>(ws + off_sigma);
+    uint64_t *scratch = reinterpret_cast<uint64_t *>(ws + off_scratch);
     for (int g = 0; g < G && e == hipSuccess; ++g) {
         const int c = g % p.n_points;
         const int64_t items = (npts[c] + kWave - 1) / kWave;
-        e = launch_embed(x, y, nullptr, dt + g, 1, base, p.n_trials, p.n_samples, p.d_y, p.d_x, p.tau, p.u,
+        if (sorted) {
+            e = launch_sort(y, nullptr, ds + g, 1, sigma, scratch, p.n_trials, p.n_samples, st);
+            if (e != hipSuccess)
+                break;
+        }
+        e = launch_embed(x, y, nullptr, sigma, dt + g, 1, base, p.n_trials, p.n_samples, p.d_y, p.d_x, p.tau, p.u,
                          ctr + 4 * g + 1, st);
         if (e != hipSuccess)
             break;
@@ -281,6 +312,7 @@ te_status Plan::estimate_plain(const float *x, const float *y, char *ws, size_t 
         a.k = p.k;
         a.counter = ctr + 4 * g;
         a.partial = partial;
+        a.sorted = sorted ? 1 : 0;
         e = launch_search_timed(a, p.d_y, p.d_x, cfg, grid_waves(items), st);
         if (e != hipSuccess)
             break;
@@ -321,8 +353,14 @@ size_t te_knn_counts_workspace_bytes(int32_t n_chunks, int64_t n_points_total)
     if (n_chunks < 1 || n_points_total < 0)
         return 0;
     const size_t items = (size_t)(n_points_total / kWave + n_chunks + 1);
-    return align_up(sizeof(ChunkDesc) * n_chunks, 256) + align_up(sizeof(int32_t) * n_chunks, 256) +
-           align_up(sizeof(double) * items, 256) + align_up(sizeof(double) * n_chunks, 256) + 256 + 256;
+    // sorted copy of the points (up to 9 coordinates), maps, sort scratch (bounded by 2x points rounded up)
+    const size_t copy = align_up(sizeof(float) * (size_t)n_points_total * (1 + kMaxDimY + kMaxDimX), 256);
+    const size_t maps = align_up(sizeof(int32_t) * (size_t)n_points_total, 256);
+    const size_t scratch = align_up(sizeof(uint64_t) * (2 * (size_t)n_points_total + (size_t)n_chunks), 256);
+    const size_t tables = align_up((sizeof(ChunkDesc) + sizeof(int32_t) + sizeof(SortTask) + sizeof(GatherTask)) *
+                                   (size_t)n_chunks + 64, 256);
+    return tables + align_up(sizeof(double) * items, 256) + align_up(sizeof(double) * n_chunks, 256) + 256 + copy +
+           maps + scratch + 256;
 }
 
 te_status te_knn_counts(const float *pts, int64_t dim_stride, const int64_t *offsets, int32_t n_chunks, int32_t d_y,
@@ -339,37 +377,67 @@ te_status te_knn_counts(const float *pts, int64_t dim_stride, const int64_t *off
     const int64_t total = offsets[n_chunks];
     if (offsets[0] != 0 || total > dim_stride)
         return fail(TE_ERR_INVALID, "offsets must start at 0 and end at or below dim_stride");
-    int64_t items = 0;
+    const int D = 1 + d_y + d_x;
+    const bool sorted = sorting_enabled();
+    int64_t items = 0, n_scratch = 0;
     std::vector<ChunkDesc> chunks(n_chunks);
+    std::vector<SortTask> sorts(n_chunks);
+    std::vector<GatherTask> gathers(n_chunks);
     for (int c = 0; c < n_chunks; ++c) {
         const int64_t n = offsets[c + 1] - offsets[c];
         if (n <= k || n > (1 << 30))
             return fail(TE_ERR_INVALID, "chunk %d has %lld points; need k < n <= 2^30", c, (long long)n);
         ChunkDesc d{};
-        d.tp = offsets[c];
-        d.s = offsets[c] + (int64_t)(1 + d_y) * dim_stride;
-        d.ld = dim_stride;
+        if (sorted) {
+            // searched in a sorted copy: coordinate m of sorted point q at copy[offsets[c] * D + m * n + q]
+            d.tp = offsets[c] * D;
+            d.s = offsets[c] * D + (int64_t)(1 + d_y) * n;
+            d.ld = n;
+            d.perm = offsets[c];
+        } else {
+            d.tp = offsets[c];
+            d.s = offsets[c] + (int64_t)(1 + d_y) * dim_stride;
+            d.ld = dim_stride;
+            d.perm = -1;
+        }
         d.out = offsets[c];
         d.n = (int32_t)n;
         d.result = c;
         chunks[c] = d;
+        SortTask so{};
+        so.sig = offsets[c];
+        so.npad = sort_npad((int)n);
+        so.scratch = -1;
+        if (so.npad > kSortLds) {
+            so.scratch = n_scratch;
+            n_scratch += so.npad;
+        }
+        so.key_off = offsets[c] + dim_stride;        // coordinate 1: first target-past coordinate
+        so.mode = 1;
+        so.n = (int32_t)n;
+        sorts[c] = so;
+        GatherTask gt{};
+        gt.src = offsets[c];
+        gt.ld = dim_stride;
+        gt.dst = offsets[c] * D;
+        gt.sig = offsets[c];
+        gt.n = (int32_t)n;
+        gathers[c] = gt;
     }
     // longest first
     std::vector<int> order(n_chunks);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return chunks[a].n > chunks[b].n; });
-    std::vector<ChunkDesc> sorted(n_chunks);
+    std::vector<ChunkDesc> sorted_chunks(n_chunks);
     std::vector<int32_t> starts(n_chunks);
     for (int i = 0; i < n_chunks; ++i) {
-        sorted[i] = chunks[order[i]];
-        sorted[i].item0 = (int32_t)items;
-        sorted[i].block0 = 0;
-        sorted[i].pbase = items;
+        sorted_chunks[i] = chunks[order[i]];
+        sorted_chunks[i].item0 = (int32_t)items;
+        sorted_chunks[i].block0 = 0;
+        sorted_chunks[i].pbase = items;
         starts[i] = (int32_t)items;
-        items += (sorted[i].n + kWave - 1) / kWave;
+        items += (sorted_chunks[i].n + kWave - 1) / kWave;
     }
-    if (ws_bytes < te_knn_counts_workspace_bytes(n_chunks, total))
-        return fail(TE_ERR_NOMEM, "workspace too small");
     DeviceInfo dev;
     te_status s = current_device(&dev);
     if (s != TE_OK)
@@ -378,28 +446,50 @@ te_status te_knn_counts(const float *pts, int64_t dim_stride, const int64_t *off
     char *ws = static_cast<char *>(ws_);
     size_t o = 0;
     const size_t off_chunks = o;
-    o = align_up(o + sizeof(ChunkDesc) * n_chunks, 256);
+    o = align_up(o + sizeof(ChunkDesc) * n_chunks, 16);
     const size_t off_items = o;
-    o = align_up(o + sizeof(int32_t) * n_chunks, 256);
+    o = align_up(o + sizeof(int32_t) * n_chunks, 16);
+    const size_t off_sorts = o;
+    o = align_up(o + sizeof(SortTask) * n_chunks, 16);
+    const size_t off_gathers = o;
+    o = align_up(o + sizeof(GatherTask) * n_chunks, 256);
+    const size_t tbytes = o;
     const size_t off_partial = o;
     o = align_up(o + sizeof(double) * (size_t)items, 256);
     const size_t off_results = o;
     o = align_up(o + sizeof(double) * n_chunks, 256);
     const size_t off_ctr = o;
-    const size_t tbytes = off_partial;
+    o += 256;
+    const size_t off_copy = o;
+    o = align_up(o + (sorted ? sizeof(float) * (size_t)total * D : 0), 256);
+    const size_t off_sigma = o;
+    o = align_up(o + (sorted ? sizeof(int32_t) * (size_t)total : 0), 256);
+    const size_t off_scratch = o;
+    o = align_up(o + (sorted ? sizeof(uint64_t) * (size_t)n_scratch : 0), 256);
+    if (ws_bytes < o)
+        return fail(TE_ERR_NOMEM, "workspace too small (%zu < %zu bytes)", ws_bytes, o);
     hipStream_t st = (hipStream_t)hip_stream;
     const size_t out_off = align_up(tbytes, 256);
     char *stg = static_cast<char *>(g_knn_pool.take(out_off + sizeof(double) * n_chunks + 64));
     if (!stg)
         return fail(TE_ERR_NOMEM, "pinned staging allocation failed");
-    std::memcpy(stg + off_chunks, sorted.data(), sizeof(ChunkDesc) * n_chunks);
+    std::memcpy(stg + off_chunks, sorted_chunks.data(), sizeof(ChunkDesc) * n_chunks);
     std::memcpy(stg + off_items, starts.data(), sizeof(int32_t) * n_chunks);
+    std::memcpy(stg + off_sorts, sorts.data(), sizeof(SortTask) * n_chunks);
+    std::memcpy(stg + off_gathers, gathers.data(), sizeof(GatherTask) * n_chunks);
     hipError_t e = hipMemcpyAsync(ws, stg, tbytes, hipMemcpyHostToDevice, st);
     int32_t *ctr = reinterpret_cast<int32_t *>(ws + off_ctr);
+    int32_t *sigma = reinterpret_cast<int32_t *>(ws + off_sigma);
     if (e == hipSuccess)
         e = launch_fill_i32(ctr, 0, 4, st);
+    if (e == hipSuccess && sorted)
+        e = launch_sort(nullptr, pts, reinterpret_cast<const SortTask *>(ws + off_sorts), n_chunks, sigma,
+                        reinterpret_cast<uint64_t *>(ws + off_scratch), 0, 0, st);
+    if (e == hipSuccess && sorted)
+        e = launch_gather(pts, reinterpret_cast<const GatherTask *>(ws + off_gathers), n_chunks, sigma,
+                          reinterpret_cast<float *>(ws + off_copy), D, st);
     SearchArgs a{};
-    a.base = pts;
+    a.base = sorted ? reinterpret_cast<const float *>(ws + off_copy) : pts;
     a.chunks = reinterpret_cast<const ChunkDesc *>(ws + off_chunks);
     a.item_start = reinterpret_cast<const int32_t *>(ws + off_items);
     a.n_chunks = n_chunks;
@@ -410,6 +500,8 @@ te_status te_knn_counts(const float *pts, int64_t dim_stride, const int64_t *off
     a.eps_out = eps;
     a.cnt_out = counts;
     a.cnt_stride = total;
+    a.perm_base = sigma;
+    a.sorted = sorted ? 1 : 0;
     if (e == hipSuccess) {
         const int64_t full = (int64_t)dev.n_cu * cfg.wg_per_cu * cfg.waves_per_wg;
         e = launch_search_timed(a, d_y, d_x, cfg, (int)std::max<int64_t>(1, std::min<int64_t>(full, items)), st);

@@ -25,6 +25,7 @@ struct ChunkDesc {
     int64_t ld;       // stride between coordinates, in floats
     int64_t out;      // per-point output offset (eps / counts), or -1
     int64_t pbase;    // index in the partial-sum array of the chunk's block 0
+    int64_t perm;     // offset in perm_base of the sorted-to-original point map, or -1
     int32_t n;        // points in the chunk
     int32_t item0;    // launch work-item index of the first scheduled block
     int32_t block0;   // first scheduled block (64 references) of the chunk
@@ -37,9 +38,29 @@ struct EmbedTask {
     int64_t tp;       // float offset of the target block, or -1
     int64_t s;        // float offset of the source block
     int64_t perm;     // int32 offset of the source permutation row, or -1 (identity)
+    int64_t sig;      // int32 offset of the window's sorted-to-original point map, or -1 (identity)
     int32_t pair, w, W, Rc;
     int32_t n;        // Rc * W
     int32_t pad_;
+};
+
+// Sorting of one search space by its first target-past coordinate p0.  The
+// result sigma[sig + q] is the original index of the point at sorted position q.
+// Keys are (order-preserving bits of p0) << 32 | original index: a total order,
+// so the permutation is unique.
+struct SortTask {
+    int64_t sig;      // int32 offset of the output map
+    int64_t scratch;  // uint64 offset of global key scratch (npad > kSortLds), else -1
+    int64_t key_off;  // mode 1: float offset of the key coordinate (point q at key_off + q)
+    int32_t mode;     // 0: key = y[pair][r][t'-1] of window point q = r W + (t' - w); 1: stored coordinate
+    int32_t pair, w, W, Rc, n, npad, pad_;
+};
+constexpr int kSortLds = 4096;    // keys sorted in LDS up to this many (padded) points
+
+// Copy of one pre-embedded chunk into sorted order: dst[dst + m n + q] = src[src + m ld + sigma[sig + q]].
+struct GatherTask {
+    int64_t src, ld, dst, sig;
+    int32_t n, pad_;
 };
 
 // Arguments of the search kernel (passed by value; read from the kernarg segment).
@@ -56,6 +77,9 @@ struct SearchArgs {
     float *eps_out;             // optional per-point radius
     int32_t *cnt_out;           // optional per-point counts [3][cnt_stride]
     int64_t cnt_stride;
+    const int32_t *perm_base;   // sorted-to-original point maps (per-point outputs only)
+    int32_t sorted;             // chunks are sorted by the first target-past coordinate
+    int32_t pad2_;
 };
 
 // Tunable launch shape of the search kernel.
@@ -73,9 +97,13 @@ struct DeviceInfo {
 
 // Kernel launchers (te_kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
-hipError_t launch_embed(const float *x, const float *y, const int32_t *perms, const EmbedTask *tasks,
-                        int n_tasks, float *base, int R, int T, int d_y, int d_x, int tau, int u,
-                        int32_t *err, hipStream_t st);
+hipError_t launch_embed(const float *x, const float *y, const int32_t *perms, const int32_t *sigma,
+                        const EmbedTask *tasks, int n_tasks, float *base, int R, int T, int d_y, int d_x, int tau,
+                        int u, int32_t *err, hipStream_t st);
+hipError_t launch_sort(const float *y, const float *pts, const SortTask *tasks, int n_tasks, int32_t *sigma,
+                       uint64_t *scratch, int R, int T, hipStream_t st);
+hipError_t launch_gather(const float *src, const GatherTask *tasks, int n_tasks, const int32_t *sigma, float *dst,
+                         int D, hipStream_t st);
 hipError_t launch_check_perms(const int32_t *perms, const int64_t *rows, const int32_t *rc, int n_rows,
                               int32_t *err, hipStream_t st);
 hipError_t launch_search(const SearchArgs &a, int d_y, int d_x, const SearchConfig &cfg, int grid_waves,

@@ -193,7 +193,7 @@ __device__ __forceinline__ int find_chunk(const int32_t *item_start, int n_chunk
 
 // ---------------------------------------------------------------- the search
 
-template <int DY, int DX, int KP1, bool GENERIC, int SLOTS>
+template <int DY, int DX, int KP1, bool GENERIC, int SLOTS, bool SORTED>
 __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs a)
 {
     constexpr int D = 1 + DY + DX;
@@ -219,6 +219,7 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
             cd.ld = uload_l(reinterpret_cast<const int64_t *>(w + offsetof(ChunkDesc, ld)));
             cd.out = uload_l(reinterpret_cast<const int64_t *>(w + offsetof(ChunkDesc, out)));
             cd.pbase = uload_l(reinterpret_cast<const int64_t *>(w + offsetof(ChunkDesc, pbase)));
+            cd.perm = uload_l(reinterpret_cast<const int64_t *>(w + offsetof(ChunkDesc, perm)));
             cd.n = uload_i(reinterpret_cast<const int32_t *>(w + offsetof(ChunkDesc, n)));
             cd.item0 = uload_i(reinterpret_cast<const int32_t *>(w + offsetof(ChunkDesc, item0)));
             cd.block0 = uload_i(reinterpret_cast<const int32_t *>(w + offsetof(ChunkDesc, block0)));
@@ -242,8 +243,21 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
             best[s] = kInf;
         float thr = kInf;
 
-        int j = 0;
-        for (; j + 4 <= n; j += 4) {
+        // current k+1-th distance of this lane: a candidate can only enter the
+        // list if its joint distance is strictly below it
+        auto cur = [&]() { return GENERIC ? thr : best[KP1 - 1]; };
+        auto visit = [&](const float (&c)[D]) {
+            const PairDist<DY, DX> d = pair_dist<DY, DX>(ref, c);
+            const float dj = fmaxf(d.t, fmaxf(d.p, d.s));
+            if (ballot(dj < cur())) {
+                keep_branch();
+                insert_sorted<KP1>(best, dj);
+                if (GENERIC)
+                    thr = kth<KP1, GENERIC>(best, k);
+            }
+        };
+        // four consecutive candidates j..j+3 (scalar loads, one per coordinate)
+        auto visit4 = [&](int j) {
             float c[4][D];
 #pragma unroll
             for (int m = 0; m < D; ++m) {
@@ -254,33 +268,63 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                 c[3][m] = v.w;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const PairDist<DY, DX> d = pair_dist<DY, DX>(ref, c[u]);
-                const float dj = fmaxf(d.t, fmaxf(d.p, d.s));
-                if (ballot(dj < (GENERIC ? thr : best[KP1 - 1]))) {
-                    keep_branch();
-                    insert_sorted<KP1>(best, dj);
-                    if (GENERIC)
-                        thr = kth<KP1, GENERIC>(best, k);
-                }
-            }
-        }
-        for (; j < n; ++j) {
+            for (int u = 0; u < 4; ++u)
+                visit(c[u]);
+        };
+        auto visit1 = [&](int j) {
             float c[D];
 #pragma unroll
             for (int m = 0; m < D; ++m)
                 c[m] = uload(cp.p[m] + j);
-            const PairDist<DY, DX> d = pair_dist<DY, DX>(ref, c);
-            const float dj = fmaxf(d.t, fmaxf(d.p, d.s));
-            if (ballot(dj < (GENERIC ? thr : best[KP1 - 1]))) {
-                keep_branch();
-                insert_sorted<KP1>(best, dj);
-                if (GENERIC)
-                    thr = kth<KP1, GENERIC>(best, k);
+            visit(c);
+        };
+        // In a chunk sorted by the first target-past coordinate p0, the joint
+        // distance to candidate j is at least |fl32(p0_i - p0_j)|, which grows
+        // monotonically away from the reference block (rounding is monotone).
+        // Once no lane can still improve at the nearest remaining candidate of a
+        // direction, no later candidate in that direction can either.
+        auto may_improve = [&](int j) { return ballot(absdiff(ref[1], uload(cp.p[1] + j)) < cur()) != 0; };
+
+        if (!SORTED) {
+            int j = 0;
+            for (; j + 4 <= n; j += 4)
+                visit4(j);
+            for (; j < n; ++j)
+                visit1(j);
+        } else {
+            const int e0 = min(n, r0 + kWave);
+            int j = r0;                                   // the block's own points first
+            for (; j + 4 <= e0; j += 4)
+                visit4(j);
+            for (; j < e0; ++j)
+                visit1(j);
+            for (j = e0; j + 4 <= n; j += 4) {            // forward: p0 increasing
+                if (!may_improve(j)) {
+                    j = n + 1;
+                    break;
+                }
+                visit4(j);
+            }
+            for (; j < n; ++j) {
+                if (!may_improve(j))
+                    break;
+                visit1(j);
+            }
+            for (j = r0; j >= 4; j -= 4) {                // backward: p0 decreasing
+                if (!may_improve(j - 1)) {
+                    j = -1;
+                    break;
+                }
+                visit4(j - 4);
+            }
+            for (; j > 0; --j) {
+                if (!may_improve(j - 1))
+                    break;
+                visit1(j - 1);
             }
         }
         // k+1-th smallest including self (distance 0) = k-th neighbour without self
-        const float eps = GENERIC ? thr : best[KP1 - 1];
+        const float eps = cur();
 
         // ---- pass 2: lane = candidate, references uniform
         // Each lane parks its reference row (coordinates, then the radius) in
@@ -294,15 +338,34 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
         myrows[lane * RW + D] = eps;
         __builtin_amdgcn_wave_barrier();
 
+        // Candidate range [lo, hi): in a sorted chunk every point outside it is at
+        // |fl32(p0_i - p0_j)| >= eps_i from every reference of the block, hence
+        // outside all three marginal balls (each contains the target-past block).
+        int lo = 0, hi = n;
+        if (SORTED) {
+            hi = min(n, r0 + kWave);
+            while (hi < n) {
+                if (!ballot(valid && absdiff(ref[1], uload(cp.p[1] + hi)) < eps))
+                    break;
+                hi = min(n, hi + kWave);
+            }
+            lo = r0;
+            while (lo > 0) {
+                if (!ballot(valid && absdiff(ref[1], uload(cp.p[1] + lo - 1)) < eps))
+                    break;
+                lo = max(0, lo - kWave);
+            }
+        }
+
         const int nref = min(kWave, n - r0);
         uint32_t accP = 0, accTP = 0, accPS = 0;
-        for (int t0 = 0; t0 < n; t0 += kWave * SLOTS) {
+        for (int t0 = lo; t0 < hi; t0 += kWave * SLOTS) {
             float cand[SLOTS][D];
 #pragma unroll
             for (int sl = 0; sl < SLOTS; ++sl) {
                 const int idx = t0 + sl * kWave + lane;
-                const bool ok = idx < n;
-                const int ic = ok ? idx : n - 1;       // in-bounds load, padded lanes masked below
+                const bool ok = idx < hi;
+                const int ic = ok ? idx : n - 1;       // in-bounds load, lanes past the range masked below
 #pragma unroll
                 for (int m = 0; m < D; ++m) {
                     const float v = cp.p[m][ic];
@@ -353,10 +416,12 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
         if (lane == 0)
             a.partial[cd.pbase + blk] = sum;
         if (a.eps_out != nullptr && cd.out >= 0 && valid) {
-            a.eps_out[cd.out + i] = eps;
-            a.cnt_out[cd.out + i] = nP;
-            a.cnt_out[a.cnt_stride + cd.out + i] = nTP;
-            a.cnt_out[2 * a.cnt_stride + cd.out + i] = nPS;
+            // per-point outputs go to the point's index before sorting
+            const int o = (cd.perm >= 0) ? a.perm_base[cd.perm + i] : i;
+            a.eps_out[cd.out + o] = eps;
+            a.cnt_out[cd.out + o] = nP;
+            a.cnt_out[a.cnt_stride + cd.out + o] = nTP;
+            a.cnt_out[2 * a.cnt_stride + cd.out + o] = nPS;
         }
     }
 }
@@ -385,17 +450,26 @@ __global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t n)
 }
 
 __global__ void embed_kernel(const float *__restrict__ x, const float *__restrict__ y,
-                             const int32_t *__restrict__ perms, const EmbedTask *__restrict__ tasks,
-                             float *__restrict__ base, int R, int T, int d_y, int d_x, int tau, int u,
-                             int32_t *err)
+                             const int32_t *__restrict__ perms, const int32_t *__restrict__ sigma,
+                             const EmbedTask *__restrict__ tasks, float *__restrict__ base, int R, int T, int d_y,
+                             int d_x, int tau, int u, int32_t *err)
 {
     const EmbedTask tk = tasks[blockIdx.x];
     const int n = tk.n;
     const int64_t pr = (int64_t)tk.pair * R;
     bool bad = false;
     for (int q = threadIdx.x; q < n; q += blockDim.x) {
-        const int r = q / tk.W;
-        const int t = tk.w + (q - r * tk.W);
+        // position q of the (sorted) chunk holds window point qo = r W + (t' - w)
+        int qo = q;
+        if (tk.sig >= 0) {
+            qo = sigma[tk.sig + q];
+            if (qo < 0 || qo >= n) {   // cannot happen for maps made by sort_kernel; keep reads in bounds
+                bad = true;
+                qo = q;
+            }
+        }
+        const int r = qo / tk.W;
+        const int t = tk.w + (qo - r * tk.W);
         int rs = r;
         if (tk.perm >= 0) {
             rs = perms[tk.perm + r];
@@ -424,6 +498,72 @@ __global__ void embed_kernel(const float *__restrict__ x, const float *__restric
     }
     if (bad)
         atomicOr(err, 1);
+}
+
+// Order-preserving unsigned image of a float (negative values reversed), joined
+// with the point index so that every key is distinct.
+__device__ __forceinline__ uint64_t sort_key(float f, uint32_t q)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return ((uint64_t)u << 32) | q;
+}
+
+// One workgroup sorts one search space by its first target-past coordinate
+// (bitonic network over npad = 2^m keys, padding keys sort last; in LDS up to
+// kSortLds keys, else in global scratch).
+__global__ void __launch_bounds__(1024) sort_kernel(const float *__restrict__ y, const float *__restrict__ pts,
+                                                    const SortTask *__restrict__ tasks, int32_t *__restrict__ sigma,
+                                                    uint64_t *__restrict__ scratch, int R, int T)
+{
+    __shared__ uint64_t lds[kSortLds];
+    const SortTask tk = tasks[blockIdx.x];
+    const int np = tk.npad;
+    uint64_t *A = (np <= kSortLds) ? lds : scratch + tk.scratch;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        uint64_t key = ~0ull;
+        if (i < tk.n) {
+            float f;
+            if (tk.mode == 0) {
+                const int r = i / tk.W;
+                const int t = tk.w + (i - r * tk.W);
+                f = y[((int64_t)tk.pair * R + r) * T + t - 1];
+            } else {
+                f = pts[tk.key_off + i];
+            }
+            key = sort_key(f, (uint32_t)i);
+        }
+        A[i] = key;
+    }
+    __syncthreads();
+    for (int kk = 2; kk <= np; kk <<= 1)
+        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+            for (int i = threadIdx.x; i < np; i += blockDim.x) {
+                const int l = i ^ jj;
+                if (l > i) {
+                    const uint64_t u0 = A[i], u1 = A[l];
+                    const bool up = (i & kk) == 0;
+                    if ((u0 > u1) == up) {
+                        A[i] = u1;
+                        A[l] = u0;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int i = threadIdx.x; i < tk.n; i += blockDim.x)
+        sigma[tk.sig + i] = (int32_t)(A[i] & 0xffffffffu);
+}
+
+__global__ void gather_kernel(const float *__restrict__ src, const GatherTask *__restrict__ tasks,
+                              const int32_t *__restrict__ sigma, float *__restrict__ dst, int D)
+{
+    const GatherTask tk = tasks[blockIdx.x];
+    for (int q = threadIdx.x; q < tk.n; q += blockDim.x) {
+        const int o = sigma[tk.sig + q];
+        for (int m = 0; m < D; ++m)
+            dst[tk.dst + (int64_t)m * tk.n + q] = src[tk.src + (int64_t)m * tk.ld + o];
+    }
 }
 
 // Permutation rows must be permutations of 0..Rc-1: one workgroup per row,
@@ -495,18 +635,21 @@ typedef void (*search_fn)(SearchArgs);
 
 template <int DY, int DX, int SLOTS>
 struct Table {
-    static search_fn get(bool generic)
+    static search_fn get(bool generic, bool sorted)
     {
-        return generic ? search_kernel<DY, DX, kMaxK + 1, true, SLOTS>
-                       : search_kernel<DY, DX, 5, false, SLOTS>;
+        if (sorted)
+            return generic ? search_kernel<DY, DX, kMaxK + 1, true, SLOTS, true>
+                           : search_kernel<DY, DX, 5, false, SLOTS, true>;
+        return generic ? search_kernel<DY, DX, kMaxK + 1, true, SLOTS, false>
+                       : search_kernel<DY, DX, 5, false, SLOTS, false>;
     }
 };
 
 template <int SLOTS>
-search_fn pick(int d_y, int d_x, bool generic)
+search_fn pick(int d_y, int d_x, bool generic, bool sorted)
 {
 #define TE_CASE(A, B) \
-    if (d_y == A && d_x == B) return Table<A, B, SLOTS>::get(generic);
+    if (d_y == A && d_x == B) return Table<A, B, SLOTS>::get(generic, sorted);
     TE_CASE(1, 1) TE_CASE(1, 2) TE_CASE(1, 3) TE_CASE(1, 4)
     TE_CASE(2, 1) TE_CASE(2, 2) TE_CASE(2, 3) TE_CASE(2, 4)
     TE_CASE(3, 1) TE_CASE(3, 2) TE_CASE(3, 3) TE_CASE(3, 4)
@@ -515,28 +658,28 @@ search_fn pick(int d_y, int d_x, bool generic)
     return nullptr;
 }
 
-search_fn pick_any(int d_y, int d_x, int k, int slots)
+search_fn pick_any(int d_y, int d_x, int k, int slots, bool sorted)
 {
     const bool generic = (k != 4);
     if (k < 1 || k > kMaxK)
         return nullptr;
     if (slots == 4)
-        return pick<4>(d_y, d_x, generic);
+        return pick<4>(d_y, d_x, generic, sorted);
     if (slots == 8)
-        return pick<8>(d_y, d_x, generic);
+        return pick<8>(d_y, d_x, generic, sorted);
     if (slots == 16)
-        return pick<16>(d_y, d_x, generic);
+        return pick<16>(d_y, d_x, generic, sorted);
     return nullptr;
 }
 
 }  // namespace
 
-bool search_supported(int d_y, int d_x, int k, int slots) { return pick_any(d_y, d_x, k, slots) != nullptr; }
+bool search_supported(int d_y, int d_x, int k, int slots) { return pick_any(d_y, d_x, k, slots, false) != nullptr; }
 
 // Resident workgroups per compute unit for the chosen search variant (0 if unknown).
 int search_occupancy(int d_y, int d_x, int k, int slots, int waves_per_wg)
 {
-    search_fn f = pick_any(d_y, d_x, k, slots);
+    search_fn f = pick_any(d_y, d_x, k, slots, true);
     if (!f)
         return 0;
     int blocks = 0;
@@ -548,7 +691,7 @@ int search_occupancy(int d_y, int d_x, int k, int slots, int waves_per_wg)
 hipError_t launch_search(const SearchArgs &a, int d_y, int d_x, const SearchConfig &cfg, int grid_waves,
                          hipStream_t st)
 {
-    search_fn f = pick_any(d_y, d_x, a.k, cfg.slots);
+    search_fn f = pick_any(d_y, d_x, a.k, cfg.slots, a.sorted != 0);
     if (!f)
         return hipErrorInvalidValue;
     const int wpg = cfg.waves_per_wg;
@@ -573,14 +716,32 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_embed(const float *x, const float *y, const int32_t *perms, const EmbedTask *tasks,
-                        int n_tasks, float *base, int R, int T, int d_y, int d_x, int tau, int u,
-                        int32_t *err, hipStream_t st)
+hipError_t launch_embed(const float *x, const float *y, const int32_t *perms, const int32_t *sigma,
+                        const EmbedTask *tasks, int n_tasks, float *base, int R, int T, int d_y, int d_x, int tau,
+                        int u, int32_t *err, hipStream_t st)
 {
     if (n_tasks <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(embed_kernel, dim3(n_tasks), dim3(256), 0, st, x, y, perms, tasks, base, R, T, d_y,
+    hipLaunchKernelGGL(embed_kernel, dim3(n_tasks), dim3(256), 0, st, x, y, perms, sigma, tasks, base, R, T, d_y,
                        d_x, tau, u, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort(const float *y, const float *pts, const SortTask *tasks, int n_tasks, int32_t *sigma,
+                       uint64_t *scratch, int R, int T, hipStream_t st)
+{
+    if (n_tasks <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(sort_kernel, dim3(n_tasks), dim3(1024), 0, st, y, pts, tasks, sigma, scratch, R, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const float *src, const GatherTask *tasks, int n_tasks, const int32_t *sigma, float *dst,
+                         int D, hipStream_t st)
+{
+    if (n_tasks <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(gather_kernel, dim3(n_tasks), dim3(256), 0, st, src, tasks, sigma, dst, D);
     return hipGetLastError();
 }
 

@@ -20,6 +20,8 @@ te_status current_device(DeviceInfo *out);
 SearchConfig default_config(const DeviceInfo &dev, int d_y, int d_x, int k, int64_t n);
 size_t align_up(size_t v, size_t a);
 int size_bucket(int64_t n);
+bool sorting_enabled();
+int sort_npad(int n);
 
 // A set of chunks laid out in one device workspace, with the host copy of its
 // tables.  Chunks are stored in schedule (longest-first) order.
@@ -35,10 +37,14 @@ struct Batch {
     std::vector<EmbedTask> tasks;
     std::vector<int64_t> perm_rows;
     std::vector<int32_t> perm_rc;
+    std::vector<SortTask> sorts;          // one per window group (empty when chunks are not sorted)
+    int64_t n_sigma = 0;                  // int32 entries of the sorted-to-original maps
+    int64_t n_scratch = 0;                // uint64 sort scratch entries
     int64_t n_items = 0;
     // byte offsets inside the workspace
     size_t off_coords = 0, off_tables = 0, off_chunks = 0, off_items = 0, off_tasks = 0, off_prow = 0,
-           off_prc = 0, off_partial = 0, off_results = 0, off_pv = 0, off_ctr = 0;
+           off_prc = 0, off_sorts = 0, off_partial = 0, off_results = 0, off_pv = 0, off_ctr = 0, off_sigma = 0,
+           off_scratch = 0;
     size_t tables_bytes = 0;
     size_t total_bytes = 0;
     std::vector<char> host_tables;
@@ -73,6 +79,7 @@ struct GraphEntry {
 
 struct Plan {
     te_problem p{};
+    bool sorted = true;                   // chunks sorted by the first target-past coordinate (TE_NO_SORT=1: off)
     std::vector<int32_t> wstart, wlen, trials;
     std::vector<int64_t> npts;
     mutable std::mutex dev_mu;

@@ -127,6 +127,7 @@ struct StepRec {
 // owns two step-table slots (arena + pinned staging) so two steps can be in flight.
 struct KernelClass {
     int d_y = 0, d_x = 0, k = 0;
+    bool sorted = true;
     hipStream_t stream[2] = {nullptr, nullptr};   // steps alternate, so one step's tail overlaps the next
     hipEvent_t last_ev[2] = {nullptr, nullptr};   // completion of the last step issued on each stream
     SearchConfig cfg{};
@@ -169,7 +170,7 @@ struct Server {
 
     te_status start();
     void loop();
-    int class_of(const te_problem &p);
+    int class_of(const te_problem &p, bool sorted);
     bool admit_one(Job *j);
     void poll_setup();
     bool issue_step(int ci);
@@ -180,12 +181,13 @@ struct Server {
 };
 
 // Kernel class of a problem, created on first use (-1 if its step tables do not fit).
-int Server::class_of(const te_problem &p)
+int Server::class_of(const te_problem &p, bool sorted)
 {
     for (size_t i = 0; i < classes.size(); ++i)
-        if (classes[i].d_y == p.d_y && classes[i].d_x == p.d_x && classes[i].k == p.k)
+        if (classes[i].d_y == p.d_y && classes[i].d_x == p.d_x && classes[i].k == p.k && classes[i].sorted == sorted)
             return (int)i;
     KernelClass c;
+    c.sorted = sorted;
     c.d_y = p.d_y;
     c.d_x = p.d_x;
     c.k = p.k;
@@ -310,9 +312,14 @@ bool Server::admit_one(Job *j)
         e = launch_check_perms(perm, reinterpret_cast<const int64_t *>(bat + b.off_prow),
                                reinterpret_cast<const int32_t *>(bat + b.off_prc), (int)b.perm_rows.size(), ctr + 1,
                                setup_stream);
+    int32_t *sigma = reinterpret_cast<int32_t *>(bat + b.off_sigma);
+    if (e == hipSuccess)
+        e = launch_sort(reinterpret_cast<const float *>(reg + j->off_y), nullptr,
+                        reinterpret_cast<const SortTask *>(bat + b.off_sorts), (int)b.sorts.size(), sigma,
+                        reinterpret_cast<uint64_t *>(bat + b.off_scratch), P.p.n_trials, P.p.n_samples, setup_stream);
     if (e == hipSuccess)
         e = launch_embed(reinterpret_cast<const float *>(reg + j->off_x), reinterpret_cast<const float *>(reg + j->off_y),
-                         perm, reinterpret_cast<const EmbedTask *>(bat + b.off_tasks), (int)b.tasks.size(),
+                         perm, sigma, reinterpret_cast<const EmbedTask *>(bat + b.off_tasks), (int)b.tasks.size(),
                          reinterpret_cast<float *>(bat + b.off_coords), P.p.n_trials, P.p.n_samples, P.p.d_y, P.p.d_x,
                          P.p.tau, P.p.u, ctr + 1, setup_stream);
     if (e == hipSuccess)
@@ -422,6 +429,7 @@ bool Server::issue_step(int ci)
     a.k = kc.k;
     a.counter = ctr;
     a.partial = reinterpret_cast<double *>(arena);
+    a.sorted = kc.sorted ? 1 : 0;
     const int64_t full = (int64_t)dev.n_cu * kc.cfg.wg_per_cu * kc.cfg.waves_per_wg;
     if (e == hipSuccess)
         e = launch_search_timed(a, kc.d_y, kc.d_x, kc.cfg, (int)std::max<int64_t>(1, std::min<int64_t>(full, items)),
@@ -687,7 +695,7 @@ te_status te_serve_submit(te_server srv, const te_problem *problem, const float 
     j->t_submit = now_s();
     if (S.t_first == 0)
         S.t_first = j->t_submit;
-    j->cls = S.class_of(P.p);
+    j->cls = S.class_of(P.p, P.sorted);
     if (j->cls < 0)
         return reject(TE_ERR_NOMEM, "the arena cannot hold the step tables of a new kernel class");
     *ticket = j->id;

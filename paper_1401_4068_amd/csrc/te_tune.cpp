@@ -100,13 +100,26 @@ te_status te_autotune(int32_t d_y, int32_t d_x, int32_t k, int32_t n_points, int
     const int D = 1 + d_y + d_x;
     const int64_t total = (int64_t)n_points * n_chunks;
     const int64_t items = (int64_t)n_chunks * ((n_points + kWave - 1) / kWave);
+    const bool sorted = sorting_enabled();
+    const int npad = sort_npad(n_points);
+    const int64_t n_scratch = npad > kSortLds ? (int64_t)npad * n_chunks : 0;
     size_t o = 0;
-    const size_t off_pts = o;
+    const size_t off_raw = o;                       // uniform random coordinates, [D][total]
+    o = align_up(o + sizeof(float) * (size_t)total * D, 256);
+    const size_t off_pts = o;                       // the same chunks sorted by coordinate 1, [chunk][D][n]
     o = align_up(o + sizeof(float) * (size_t)total * D, 256);
     const size_t off_chunks = o;
     o = align_up(o + sizeof(ChunkDesc) * n_chunks, 256);
     const size_t off_items = o;
     o = align_up(o + sizeof(int32_t) * n_chunks, 256);
+    const size_t off_sorts = o;
+    o = align_up(o + sizeof(SortTask) * n_chunks, 256);
+    const size_t off_gathers = o;
+    o = align_up(o + sizeof(GatherTask) * n_chunks, 256);
+    const size_t off_sigma = o;
+    o = align_up(o + sizeof(int32_t) * (size_t)total, 256);
+    const size_t off_scratch = o;
+    o = align_up(o + sizeof(uint64_t) * (size_t)n_scratch, 256);
     const size_t off_partial = o;
     o = align_up(o + sizeof(double) * (size_t)items, 256);
     const size_t off_ctr = o;
@@ -121,12 +134,21 @@ te_status te_autotune(int32_t d_y, int32_t d_x, int32_t k, int32_t n_points, int
     hipStream_t st = (hipStream_t)hip_stream;
     std::vector<ChunkDesc> cd(n_chunks);
     std::vector<int32_t> starts(n_chunks);
+    std::vector<SortTask> sorts(n_chunks);
+    std::vector<GatherTask> gathers(n_chunks);
     for (int c = 0; c < n_chunks; ++c) {
         ChunkDesc d{};
-        d.tp = (int64_t)c * n_points;
-        d.s = (int64_t)c * n_points + (int64_t)(1 + d_y) * total;
-        d.ld = total;
+        if (sorted) {
+            d.tp = (int64_t)c * n_points * D;
+            d.s = d.tp + (int64_t)(1 + d_y) * n_points;
+            d.ld = n_points;
+        } else {
+            d.tp = (int64_t)c * n_points;
+            d.s = (int64_t)c * n_points + (int64_t)(1 + d_y) * total;
+            d.ld = total;
+        }
         d.out = -1;
+        d.perm = -1;
         d.n = n_points;
         d.item0 = (int32_t)((int64_t)c * ((n_points + kWave - 1) / kWave));
         d.pbase = d.item0;
@@ -134,16 +156,47 @@ te_status te_autotune(int32_t d_y, int32_t d_x, int32_t k, int32_t n_points, int
         d.result = c;
         cd[c] = d;
         starts[c] = d.item0;
+        SortTask so{};
+        so.sig = (int64_t)c * n_points;
+        so.npad = npad;
+        so.scratch = npad > kSortLds ? (int64_t)c * npad : -1;
+        so.key_off = (int64_t)c * n_points + total;  // coordinate 1
+        so.mode = 1;
+        so.n = n_points;
+        sorts[c] = so;
+        GatherTask g{};
+        g.src = (int64_t)c * n_points;
+        g.ld = total;
+        g.dst = (int64_t)c * n_points * D;
+        g.sig = (int64_t)c * n_points;
+        g.n = n_points;
+        gathers[c] = g;
     }
     hipError_t e = hipMemcpy(ws + off_chunks, cd.data(), sizeof(ChunkDesc) * n_chunks, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(ws + off_items, starts.data(), sizeof(int32_t) * n_chunks, hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = launch_fill_uniform(reinterpret_cast<float *>(ws + off_pts), total * D, 0x7e5eed, st);
+        e = hipMemcpy(ws + off_sorts, sorts.data(), sizeof(SortTask) * n_chunks, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(ws + off_gathers, gathers.data(), sizeof(GatherTask) * n_chunks, hipMemcpyHostToDevice);
+    float *raw = reinterpret_cast<float *>(ws + off_raw);
+    if (e == hipSuccess)
+        e = launch_fill_uniform(raw, total * D, 0x7e5eed, st);
+    if (e == hipSuccess && sorted)
+        e = launch_sort(nullptr, raw, reinterpret_cast<const SortTask *>(ws + off_sorts), n_chunks,
+                        reinterpret_cast<int32_t *>(ws + off_sigma), reinterpret_cast<uint64_t *>(ws + off_scratch), 0,
+                        0, st);
+    if (e == hipSuccess && sorted)
+        e = launch_gather(raw, reinterpret_cast<const GatherTask *>(ws + off_gathers), n_chunks,
+                          reinterpret_cast<const int32_t *>(ws + off_sigma), reinterpret_cast<float *>(ws + off_pts), D,
+                          st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
     if (e != hipSuccess)
         return hip_fail(e, "tuning setup");
     SearchArgs a{};
-    a.base = reinterpret_cast<const float *>(ws + off_pts);
+    a.base = reinterpret_cast<const float *>(ws + (sorted ? off_pts : off_raw));
+    a.sorted = sorted ? 1 : 0;
     a.chunks = reinterpret_cast<const ChunkDesc *>(ws + off_chunks);
     a.item_start = reinterpret_cast<const int32_t *>(ws + off_items);
     a.n_chunks = n_chunks;

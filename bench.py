@@ -137,6 +137,7 @@ def batched_record(args, wl, wname):
         step()
     te.profile_enable(True)
     te.profile_read(reset=True)
+    te.profile_work(reset=True)
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -147,6 +148,7 @@ def batched_record(args, wl, wname):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     k_ms, k_n = te.profile_read(reset=True)
+    w1, w2 = te.profile_work(reset=True)
     te.profile_enable(False)
     est = wl.n_estimates()
     value = est * args.steps / dt
@@ -156,14 +158,20 @@ def batched_record(args, wl, wname):
     roof = None
     if k_n > 0:
         avg_s = k_ms / k_n / 1e3
-        ops = pairs_per_pass * ops_per_pair(D) * args.steps / k_n
+        # algorithmic ops of the pairs each launch evaluates: 2D per pass-1 pair, 2D + 2 per pass-2 pair
+        p1, p2 = w1 / k_n, w2 / k_n
+        ops = p1 * 2 * D + p2 * (2 * D + 2)
+        method_ops = pairs_per_pass * ops_per_pair(D) * args.steps / k_n
         achieved = ops / avg_s / 1e12
         roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_OPS, unit="TFLOP/s",
                     frac=round(achieved / PEAK_FP32_OPS, 4),
                     traffic=kernel_traffic() if wname == "nonlinear_ar_ensemble" else None,
-                    kernel="search_kernel<%d,%d,k=%d,slots=%d>" % (wl.d_y, wl.d_x, wl.k,
-                                                                   tuned["slots"] if tuned else 8),
+                    kernel="search_kernel<%d,%d,k=%d,slots=%d,sorted>" % (wl.d_y, wl.d_x, wl.k,
+                                                                          tuned["slots"] if tuned else 8),
                     avg_launch_ms=round(avg_s * 1e3, 4), launches=k_n, ops_per_launch=int(ops),
+                    pairs_evaluated_per_launch=[int(p1), int(p2)],
+                    method_pairs_per_launch=int(pairs_per_pass * args.steps / k_n),
+                    method_equivalent_tops=round(method_ops / avg_s / 1e12, 3),
                     frac_of_headline_157_3=round(achieved / PEAK_FP32_HEADLINE, 4))
 
     # plain per-time-point path on the same workload

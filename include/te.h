@@ -230,6 +230,10 @@ te_status te_tune_clear(void);
  * and the number of launches (reset != 0 clears the totals).  Process-wide. */
 te_status te_profile_enable(int32_t on);
 te_status te_profile_read(double *search_ms, int64_t *launches, int32_t reset);
+/* Pairs the timed search launches actually evaluated: pass 1 (radius) and pass 2
+ * (counts); with sorted search spaces these are below the method's N(N-1) per
+ * pass.  Synchronises the device. */
+te_status te_profile_work(int64_t *pass1_pairs, int64_t *pass2_pairs, int32_t reset);
 
 #ifdef __cplusplus
 }

@@ -309,5 +309,12 @@ def profile_read(reset: bool = False):
     return ms.value, n.value
 
 
+def profile_work(reset: bool = False):
+    """(pass-1 pairs, pass-2 pairs) evaluated by timed search launches since the last reset."""
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    check(lib().te_profile_work(ctypes.byref(a), ctypes.byref(b), int(bool(reset))))
+    return a.value, b.value
+
+
 def version() -> str:
     return lib().te_version().decode()

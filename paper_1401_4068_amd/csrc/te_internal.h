@@ -55,7 +55,7 @@ struct SortTask {
     int32_t mode;     // 0: key = y[pair][r][t'-1] of window point q = r W + (t' - w); 1: stored coordinate
     int32_t pair, w, W, Rc, n, npad, pad_;
 };
-constexpr int kSortLds = 4096;    // keys sorted in LDS up to this many (padded) points
+constexpr int kSortLds = 16384;   // keys sorted in LDS (128 KiB) up to this many (padded) points
 
 // Copy of one pre-embedded chunk into sorted order: dst[dst + m n + q] = src[src + m ld + sigma[sig + q]].
 struct GatherTask {
@@ -78,6 +78,7 @@ struct SearchArgs {
     int32_t *cnt_out;           // optional per-point counts [3][cnt_stride]
     int64_t cnt_stride;
     const int32_t *perm_base;   // sorted-to-original point maps (per-point outputs only)
+    unsigned long long *work;   // optional: [0] += pairs evaluated in pass 1, [1] += in pass 2
     int32_t sorted;             // chunks are sorted by the first target-past coordinate
     int32_t pad2_;
 };
@@ -112,6 +113,7 @@ hipError_t launch_reduce(const ChunkDesc *chunks, int n_chunks, const double *pa
                          const int32_t *err, double *results, hipStream_t st);
 hipError_t launch_pvalues(const double *results, int n_groups, int n_surr, double *pv, hipStream_t st);
 bool search_supported(int d_y, int d_x, int k, int slots);
+unsigned long long *work_counters();   // this device's evaluated-pair counters (measurement)
 
 // Search launch bracketed by profiling events when measurement is enabled (te_profile.cpp).
 hipError_t launch_search_timed(const SearchArgs &a, int d_y, int d_x, const SearchConfig &cfg, int grid_waves,

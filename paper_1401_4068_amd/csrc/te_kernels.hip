@@ -285,6 +285,7 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
         // direction, no later candidate in that direction can either.
         auto may_improve = [&](int j) { return ballot(absdiff(ref[1], uload(cp.p[1] + j)) < cur()) != 0; };
 
+        int visited = n;                                  // candidates examined in pass 1
         if (!SORTED) {
             int j = 0;
             for (; j + 4 <= n; j += 4)
@@ -292,6 +293,7 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
             for (; j < n; ++j)
                 visit1(j);
         } else {
+            int fwd_end = n, bwd_end = 0;
             const int e0 = min(n, r0 + kWave);
             int j = r0;                                   // the block's own points first
             for (; j + 4 <= e0; j += 4)
@@ -300,28 +302,35 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                 visit1(j);
             for (j = e0; j + 4 <= n; j += 4) {            // forward: p0 increasing
                 if (!may_improve(j)) {
+                    fwd_end = j;
                     j = n + 1;
                     break;
                 }
                 visit4(j);
             }
             for (; j < n; ++j) {
-                if (!may_improve(j))
+                if (!may_improve(j)) {
+                    fwd_end = j;
                     break;
+                }
                 visit1(j);
             }
             for (j = r0; j >= 4; j -= 4) {                // backward: p0 decreasing
                 if (!may_improve(j - 1)) {
+                    bwd_end = j;
                     j = -1;
                     break;
                 }
                 visit4(j - 4);
             }
             for (; j > 0; --j) {
-                if (!may_improve(j - 1))
+                if (!may_improve(j - 1)) {
+                    bwd_end = j;
                     break;
+                }
                 visit1(j - 1);
             }
+            visited = fwd_end - bwd_end;
         }
         // k+1-th smallest including self (distance 0) = k-th neighbour without self
         const float eps = cur();
@@ -413,8 +422,13 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
         if (valid)
             term = psi_of_count(nP) - psi_of_count(nTP) - psi_of_count(nPS);
         const double sum = wave_sum(term);
-        if (lane == 0)
+        if (lane == 0) {
             a.partial[cd.pbase + blk] = sum;
+            if (a.work != nullptr) {
+                atomicAdd(a.work, (unsigned long long)visited * (unsigned long long)nref);
+                atomicAdd(a.work + 1, (unsigned long long)(hi - lo) * (unsigned long long)nref);
+            }
+        }
         if (a.eps_out != nullptr && cd.out >= 0 && valid) {
             // per-point outputs go to the point's index before sorting
             const int o = (cd.perm >= 0) ? a.perm_base[cd.perm + i] : i;
@@ -509,9 +523,32 @@ __device__ __forceinline__ uint64_t sort_key(float f, uint32_t q)
     return ((uint64_t)u << 32) | q;
 }
 
-// One workgroup sorts one search space by its first target-past coordinate
-// (bitonic network over npad = 2^m keys, padding keys sort last; in LDS up to
-// kSortLds keys, else in global scratch).
+// One bitonic compare-exchange pass with stride jj inside stage kk over
+// elements [lo, lo + len) of A (global indices i, so the direction is that of
+// the full network).
+__device__ __forceinline__ void bitonic_pass(uint64_t *A, int base, int len, int kk, int jj, int offset)
+{
+    for (int t = threadIdx.x; t < len; t += blockDim.x) {
+        const int i = base + t;
+        const int l = i ^ jj;
+        if (l > i) {
+            const int gi = offset + i;
+            const uint64_t u0 = A[i], u1 = A[l];
+            const bool up = (gi & kk) == 0;
+            if ((u0 > u1) == up) {
+                A[i] = u1;
+                A[l] = u0;
+            }
+        }
+    }
+}
+
+// One workgroup sorts one search space by its first target-past coordinate:
+// a bitonic network over npad = 2^m keys (padding keys sort last).  Up to
+// kSortLds keys the whole network runs in LDS.  Above that the keys live in
+// global scratch; every stage's passes with stride below kSortLds only pair
+// elements of the same kSortLds-aligned tile, so each tile is loaded into LDS
+// once per stage for those passes and only the wider strides touch global memory.
 __global__ void __launch_bounds__(1024) sort_kernel(const float *__restrict__ y, const float *__restrict__ pts,
                                                     const SortTask *__restrict__ tasks, int32_t *__restrict__ sigma,
                                                     uint64_t *__restrict__ scratch, int R, int T)
@@ -536,21 +573,46 @@ __global__ void __launch_bounds__(1024) sort_kernel(const float *__restrict__ y,
         A[i] = key;
     }
     __syncthreads();
-    for (int kk = 2; kk <= np; kk <<= 1)
-        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-            for (int i = threadIdx.x; i < np; i += blockDim.x) {
-                const int l = i ^ jj;
-                if (l > i) {
-                    const uint64_t u0 = A[i], u1 = A[l];
-                    const bool up = (i & kk) == 0;
-                    if ((u0 > u1) == up) {
-                        A[i] = u1;
-                        A[l] = u0;
-                    }
-                }
+    if (np <= kSortLds) {
+        for (int kk = 2; kk <= np; kk <<= 1)
+            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                bitonic_pass(A, 0, np, kk, jj, 0);
+                __syncthreads();
             }
+    } else {
+        // stages that fit a tile: sort every tile in LDS
+        for (int t0 = 0; t0 < np; t0 += kSortLds) {
+            for (int i = threadIdx.x; i < kSortLds; i += blockDim.x)
+                lds[i] = A[t0 + i];
+            __syncthreads();
+            for (int kk = 2; kk <= kSortLds; kk <<= 1)
+                for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                    bitonic_pass(lds, 0, kSortLds, kk, jj, t0);
+                    __syncthreads();
+                }
+            for (int i = threadIdx.x; i < kSortLds; i += blockDim.x)
+                A[t0 + i] = lds[i];
             __syncthreads();
         }
+        for (int kk = 2 * kSortLds; kk <= np; kk <<= 1) {
+            for (int jj = kk >> 1; jj >= kSortLds; jj >>= 1) {
+                bitonic_pass(A, 0, np, kk, jj, 0);
+                __syncthreads();
+            }
+            for (int t0 = 0; t0 < np; t0 += kSortLds) {
+                for (int i = threadIdx.x; i < kSortLds; i += blockDim.x)
+                    lds[i] = A[t0 + i];
+                __syncthreads();
+                for (int jj = kSortLds >> 1; jj > 0; jj >>= 1) {
+                    bitonic_pass(lds, 0, kSortLds, kk, jj, t0);
+                    __syncthreads();
+                }
+                for (int i = threadIdx.x; i < kSortLds; i += blockDim.x)
+                    A[t0 + i] = lds[i];
+                __syncthreads();
+            }
+        }
+    }
     for (int i = threadIdx.x; i < tk.n; i += blockDim.x)
         sigma[tk.sig + i] = (int32_t)(A[i] & 0xffffffffu);
 }
@@ -673,6 +735,17 @@ search_fn pick_any(int d_y, int d_x, int k, int slots, bool sorted)
 }
 
 }  // namespace
+
+// Device counters of evaluated pairs for the measurement hook (one copy per device).
+__device__ unsigned long long g_work_counters[2];
+
+unsigned long long *work_counters()
+{
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_work_counters)) != hipSuccess)
+        return nullptr;
+    return static_cast<unsigned long long *>(p);
+}
 
 bool search_supported(int d_y, int d_x, int k, int slots) { return pick_any(d_y, d_x, k, slots, false) != nullptr; }
 

@@ -21,6 +21,7 @@ std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_free;
 double g_ms = 0.0;
 int64_t g_launches = 0;
+unsigned long long *g_work = nullptr;   // this device's counters of evaluated pairs (pass 1, pass 2)
 
 hipEvent_t get_event()
 {
@@ -57,8 +58,15 @@ hipError_t launch_search_timed(const SearchArgs &a, int d_y, int d_x, const Sear
     }
     if (!e0 || !e1)
         return launch_search(a, d_y, d_x, cfg, grid_waves, st);
+    SearchArgs b = a;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!g_work)
+            g_work = work_counters();
+        b.work = g_work;
+    }
     hipEventRecord(e0, st);
-    hipError_t e = launch_search(a, d_y, d_x, cfg, grid_waves, st);
+    hipError_t e = launch_search(b, d_y, d_x, cfg, grid_waves, st);
     hipEventRecord(e1, st);
     std::lock_guard<std::mutex> lk(g_mu);
     g_pending.push_back({e0, e1});
@@ -75,6 +83,24 @@ te_status te_profile_enable(int32_t on)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     g_on = on != 0;
+    return TE_OK;
+}
+
+te_status te_profile_work(int64_t *pass1_pairs, int64_t *pass2_pairs, int32_t reset)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    unsigned long long w[2] = {0, 0};
+    if (g_work) {
+        if (hipDeviceSynchronize() != hipSuccess ||
+            hipMemcpy(w, g_work, sizeof w, hipMemcpyDeviceToHost) != hipSuccess)
+            return TE_ERR_DEVICE;
+        if (reset && hipMemset(g_work, 0, sizeof w) != hipSuccess)
+            return TE_ERR_DEVICE;
+    }
+    if (pass1_pairs)
+        *pass1_pairs = (int64_t)w[0];
+    if (pass2_pairs)
+        *pass2_pairs = (int64_t)w[1];
     return TE_OK;
 }
 

@@ -291,3 +291,24 @@ def test_autotune_records_a_valid_shape(te, tmp_path):
     te.tune_clear()
     b = te.Plan.from_workload(wl).estimate(x, y)
     np.testing.assert_array_equal(a, b)
+
+
+def test_knn_counts_chunk_larger_than_lds_sort(te):
+    """N = 17 000 pads to 32 768 keys: the sort runs in global scratch with LDS tiles."""
+    _knn_case(te, [17000, 700], 2, 2, 4, "gauss", seed=11)
+
+
+def test_work_counters_and_pruning(te):
+    """Sorted search spaces evaluate fewer pairs than N(N-1) per pass; counters report them."""
+    wl = synth.nonlinear_ensemble(R=300, T=60, n_points=4, window=10)
+    x, y, _ = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    te.profile_enable(True)
+    te.profile_work(reset=True)
+    plan.surrogates(x, y)
+    w1, w2 = te.profile_work(reset=True)
+    te.profile_enable(False)
+    n = wl.chunk_sizes()
+    method = int(np.sum(n * (n - 1)))
+    say("evaluated", w1, w2, "method", method)
+    assert 0 < w1 <= method + int(np.sum(n)) and 0 < w2 <= method + int(np.sum(n))

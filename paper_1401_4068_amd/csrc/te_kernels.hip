@@ -382,6 +382,12 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                 }
             }
             uint32_t tP = 0, tTP = 0, tPS = 0;
+            // p0 range of this tile's candidates (sorted chunks): first and last in range
+            float tlo = 0.0f, thi = 0.0f;
+            if (SORTED) {
+                tlo = uload(cp.p[1] + t0);
+                thi = uload(cp.p[1] + min(t0 + kWave * SLOTS, hi) - 1);
+            }
             for (int r = 0; r < nref; ++r) {
                 float rr[RW];
                 const f4v *rowv = reinterpret_cast<const f4v *>(myrows + r * RW);
@@ -394,6 +400,10 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                     rr[4 * v + 3] = x.w;
                 }
                 const float er = rr[D];
+                // the whole tile lies at |fl32(p0_r - p0_j)| >= eps_r from this reference:
+                // nothing to count for it here (its lane keeps the zero it starts the tile with)
+                if (SORTED && ballot(tlo - rr[1] >= er || rr[1] - thi >= er))
+                    continue;
                 uint32_t sP = 0, sTP = 0, sPS = 0;
 #pragma unroll
                 for (int sl = 0; sl < SLOTS; ++sl) {

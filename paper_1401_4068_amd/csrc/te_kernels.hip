@@ -368,6 +368,7 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
 
         const int nref = min(kWave, n - r0);
         uint32_t accP = 0, accTP = 0, accPS = 0;
+        unsigned long long evaluated2 = 0;                // candidate-reference pairs examined in pass 2
         for (int t0 = lo; t0 < hi; t0 += kWave * SLOTS) {
             float cand[SLOTS][D];
 #pragma unroll
@@ -404,6 +405,7 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                 // nothing to count for it here (its lane keeps the zero it starts the tile with)
                 if (SORTED && ballot(tlo - rr[1] >= er || rr[1] - thi >= er))
                     continue;
+                evaluated2 += (unsigned long long)min(kWave * SLOTS, hi - t0);
                 uint32_t sP = 0, sTP = 0, sPS = 0;
 #pragma unroll
                 for (int sl = 0; sl < SLOTS; ++sl) {
@@ -436,12 +438,14 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
             a.partial[cd.pbase + blk] = sum;
             if (a.work != nullptr) {
                 atomicAdd(a.work, (unsigned long long)visited * (unsigned long long)nref);
-                atomicAdd(a.work + 1, (unsigned long long)(hi - lo) * (unsigned long long)nref);
+                atomicAdd(a.work + 1, evaluated2);
             }
         }
         if (a.eps_out != nullptr && cd.out >= 0 && valid) {
             // per-point outputs go to the point's index before sorting
-            const int o = (cd.perm >= 0) ? a.perm_base[cd.perm + i] : i;
+            int o = (cd.perm >= 0) ? a.perm_base[cd.perm + i] : i;
+            if (o < 0 || o >= n)         // keep writes inside the chunk's output range regardless
+                o = i;
             a.eps_out[cd.out + o] = eps;
             a.cnt_out[cd.out + o] = nP;
             a.cnt_out[a.cnt_stride + cd.out + o] = nTP;
@@ -533,22 +537,72 @@ __device__ __forceinline__ uint64_t sort_key(float f, uint32_t q)
     return ((uint64_t)u << 32) | q;
 }
 
-// One bitonic compare-exchange pass with stride jj inside stage kk over
-// elements [lo, lo + len) of A (global indices i, so the direction is that of
-// the full network).
-__device__ __forceinline__ void bitonic_pass(uint64_t *A, int base, int len, int kk, int jj, int offset)
+// One bitonic compare-exchange pass with stride jj inside stage kk over the
+// len elements of A (LDS tile or global array).  offset: global index of A[0],
+// so the sort direction is that of the full network.  Workgroup-wide: every
+// thread takes pairs across the whole range.
+__device__ __forceinline__ void bitonic_pass(uint64_t *A, int len, int kk, int jj, int offset)
 {
     for (int t = threadIdx.x; t < len; t += blockDim.x) {
-        const int i = base + t;
+        const int i = t;
         const int l = i ^ jj;
         if (l > i) {
-            const int gi = offset + i;
             const uint64_t u0 = A[i], u1 = A[l];
-            const bool up = (gi & kk) == 0;
+            const bool up = ((offset + i) & kk) == 0;
             if ((u0 > u1) == up) {
                 A[i] = u1;
                 A[l] = u0;
             }
+        }
+    }
+}
+
+// All passes of stage kk with stride jj < seg, for an LDS array split into
+// seg-sized segments of which each wave owns one (or several): partners of
+// strides below seg lie in the same segment, so a wave runs these passes back
+// to back without workgroup barriers (LDS accesses of one wave complete in order).
+__device__ __forceinline__ void bitonic_wave_passes(uint64_t *A, int len, int kk, int jstart, int seg, int offset)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int nwaves = blockDim.x / kWave;
+    for (int s0 = wave * seg; s0 < len; s0 += nwaves * seg) {
+        for (int jj = jstart; jj > 0; jj >>= 1) {
+            for (int t = lane; t < seg; t += kWave) {
+                const int i = s0 + t;
+                const int l = i ^ jj;
+                if (l > i) {
+                    const uint64_t u0 = A[i], u1 = A[l];
+                    const bool up = ((offset + i) & kk) == 0;
+                    if ((u0 > u1) == up) {
+                        A[i] = u1;
+                        A[l] = u0;
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+}
+
+// Full bitonic network over len (power of two) keys in LDS; offset as above.
+// Strides of at least one wave segment run workgroup-wide with a barrier after
+// each pass; the smaller strides of a stage run wave-locally.
+__device__ void bitonic_lds(uint64_t *A, int len, int kk_first, int kk_last, int offset)
+{
+    const int nwaves = blockDim.x / kWave;
+    const int seg = max(2, len / nwaves);        // keys per wave segment
+    for (int kk = kk_first; kk <= kk_last; kk <<= 1) {
+        int jj = kk >> 1;
+        for (; jj >= seg; jj >>= 1) {
+            bitonic_pass(A, len, kk, jj, offset);
+            __syncthreads();
+        }
+        if (jj > 0) {
+            bitonic_wave_passes(A, len, kk, jj, seg, offset);
+            __syncthreads();
         }
     }
 }
@@ -584,39 +638,36 @@ __global__ void __launch_bounds__(1024) sort_kernel(const float *__restrict__ y,
     }
     __syncthreads();
     if (np <= kSortLds) {
-        for (int kk = 2; kk <= np; kk <<= 1)
-            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-                bitonic_pass(A, 0, np, kk, jj, 0);
-                __syncthreads();
-            }
+        bitonic_lds(lds, np, 2, np, 0);
     } else {
         // stages that fit a tile: sort every tile in LDS
         for (int t0 = 0; t0 < np; t0 += kSortLds) {
             for (int i = threadIdx.x; i < kSortLds; i += blockDim.x)
                 lds[i] = A[t0 + i];
             __syncthreads();
-            for (int kk = 2; kk <= kSortLds; kk <<= 1)
-                for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-                    bitonic_pass(lds, 0, kSortLds, kk, jj, t0);
-                    __syncthreads();
-                }
+            bitonic_lds(lds, kSortLds, 2, kSortLds, t0);
             for (int i = threadIdx.x; i < kSortLds; i += blockDim.x)
                 A[t0 + i] = lds[i];
             __syncthreads();
         }
         for (int kk = 2 * kSortLds; kk <= np; kk <<= 1) {
             for (int jj = kk >> 1; jj >= kSortLds; jj >>= 1) {
-                bitonic_pass(A, 0, np, kk, jj, 0);
+                bitonic_pass(A, np, kk, jj, 0);
                 __syncthreads();
             }
             for (int t0 = 0; t0 < np; t0 += kSortLds) {
                 for (int i = threadIdx.x; i < kSortLds; i += blockDim.x)
                     lds[i] = A[t0 + i];
                 __syncthreads();
-                for (int jj = kSortLds >> 1; jj > 0; jj >>= 1) {
-                    bitonic_pass(lds, 0, kSortLds, kk, jj, t0);
+                // the remaining strides of stage kk, inside this tile
+                const int nwaves = blockDim.x / kWave;
+                const int seg = kSortLds / nwaves;
+                for (int jj = kSortLds >> 1; jj >= seg; jj >>= 1) {
+                    bitonic_pass(lds, kSortLds, kk, jj, t0);
                     __syncthreads();
                 }
+                bitonic_wave_passes(lds, kSortLds, kk, seg >> 1, seg, t0);
+                __syncthreads();
                 for (int i = threadIdx.x; i < kSortLds; i += blockDim.x)
                     A[t0 + i] = lds[i];
                 __syncthreads();
@@ -632,7 +683,9 @@ __global__ void gather_kernel(const float *__restrict__ src, const GatherTask *_
 {
     const GatherTask tk = tasks[blockIdx.x];
     for (int q = threadIdx.x; q < tk.n; q += blockDim.x) {
-        const int o = sigma[tk.sig + q];
+        int o = sigma[tk.sig + q];
+        if (o < 0 || o >= tk.n)          // maps from sort_kernel are permutations; keep reads in bounds regardless
+            o = q;
         for (int m = 0; m < D; ++m)
             dst[tk.dst + (int64_t)m * tk.n + q] = src[tk.src + (int64_t)m * tk.ld + o];
     }

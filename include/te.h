@@ -126,6 +126,20 @@ te_status te_surrogates(te_plan plan, const float *x, const float *y, const int3
                         void *ws, size_t ws_bytes, void *hip_stream, int32_t use_graph,
                         double *te_orig, double *te_surr, double *p_value);
 
+/* Local transfer entropy (the per-point quantity of eq. 17, whose average is
+ * the estimate, eq. 18): for every pooled point i of every original window,
+ *   lte_i = psi(k) + psi(n_P(i)+1) - psi(n_TP(i)+1) - psi(n_PS(i)+1),
+ * the summand of eq. 9 with psi(k) included, so the mean over a window is its
+ * estimate.  Same searches as te_estimate, all windows in one launch.
+ *   lte      device float64 [te_plan_local_size] : window g = pair * n_points + point
+ *            occupies [off[g], off[g+1]) with off from te_plan_local_offsets; points
+ *            in window order q = r W_c + (t' - w_c)
+ *   te_out   host float64 [n_pairs][n_points] (may be NULL)
+ *   ws       device workspace of ws_bytes >= the plan's full size */
+te_status te_plan_local_offsets(te_plan plan, int64_t *offsets /* host [n_pairs*n_points + 1] */);
+te_status te_local(te_plan plan, const float *x, const float *y, void *ws, size_t ws_bytes,
+                   void *hip_stream, double *lte, double *te_out);
+
 /* Kernel-level export in the shape of the paper's neighbour-search call
  * ("Input data"; "Implementation interface"): several pre-embedded chunks
  * searched in one launch.

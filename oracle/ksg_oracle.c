@@ -206,6 +206,27 @@ double ksg_te_from_counts(const int32_t *n_p, const int32_t *n_tp, const int32_t
     return ksg_digamma_int(k) + (double)(acc / (long double)N);
 }
 
+/* Local TE of each pooled point (the summand of eq. 9 with psi(k) added, the
+ * per-event quantity of eq. 17 estimated on the ensemble PDF): its mean over the
+ * points is eq. 9's estimate (eq. 18).  Harmonic numbers in long double; gamma
+ * cancels since it enters twice with each sign. */
+void ksg_local_from_counts(const int32_t *n_p, const int32_t *n_tp, const int32_t *n_ps, int N, int k,
+                           double *lte)
+{
+    for (int i = 0; i < N; ++i) {
+        long double h = 0.0L;
+        for (int m = 1; m < k; ++m)
+            h += 1.0L / (long double)m;
+        for (int m = 1; m <= n_p[i]; ++m)
+            h += 1.0L / (long double)m;
+        for (int m = 1; m <= n_tp[i]; ++m)
+            h -= 1.0L / (long double)m;
+        for (int m = 1; m <= n_ps[i]; ++m)
+            h -= 1.0L / (long double)m;
+        lte[i] = (double)h;
+    }
+}
+
 /* p = #{ s : te_surr[s] >= te_orig } / S  (NaN when S == 0) */
 double ksg_p_value(double te_orig, const double *te_surr, int S)
 {

@@ -50,6 +50,8 @@ def lib():
         L.ksg_digamma_int.restype = ctypes.c_double
         L.ksg_te_from_counts.argtypes = [i32p, i32p, i32p, ci, ci]
         L.ksg_te_from_counts.restype = ctypes.c_double
+        L.ksg_local_from_counts.argtypes = [i32p, i32p, i32p, ci, ci, f64p]
+        L.ksg_local_from_counts.restype = None
         L.ksg_p_value.argtypes = [ctypes.c_double, f64p, ci]
         L.ksg_p_value.restype = ctypes.c_double
         L.ksg_te_batch.argtypes = [f32p, f32p, ci, ci, ci, ci, ci, ci, ci, ci, ci,
@@ -125,6 +127,21 @@ def te_from_counts(cnt, k) -> float:
     N = cnt.shape[1]
     return lib().ksg_te_from_counts(_p(cnt[0], ctypes.c_int32), _p(cnt[1], ctypes.c_int32),
                                     _p(cnt[2], ctypes.c_int32), N, k)
+
+
+def local_from_counts(cnt, k) -> np.ndarray:
+    """Per-point local TE (eq. 17 on the pooled ensemble; mean = eq. 9, eq. 18)."""
+    cnt = np.ascontiguousarray(cnt, np.int32)
+    N = cnt.shape[1]
+    out = np.empty(N, np.float64)
+    lib().ksg_local_from_counts(_p(cnt[0], ctypes.c_int32), _p(cnt[1], ctypes.c_int32),
+                                _p(cnt[2], ctypes.c_int32), N, k, _p(out, ctypes.c_double))
+    return out
+
+
+def local_te(pts, d_y, d_x, k, mode=0) -> np.ndarray:
+    """Local TE of every point of one pooled chunk [N, D], in the chunk's point order."""
+    return local_from_counts(counts(pts, d_y, d_x, k, mode)[1], k)
 
 
 def p_value(te_orig: float, te_surr) -> float:

@@ -69,6 +69,8 @@ SIGNATURES = {
     "te_serve_cancel": ([_vp, ctypes.c_uint64], _st),
     "te_serve_stats": ([_vp, ctypes.POINTER(ServeStats)], _st),
     "te_serve_close": ([_vp], _st),
+    "te_plan_local_offsets": ([_vp, ctypes.POINTER(_i64)], _st),
+    "te_local": ([_vp, _vp, _vp, _vp, _sz, _vp, _vp, _dp], _st),
     "te_autotune": ([_i32, _i32, _i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                      ctypes.POINTER(_i32), _dp], _st),
     "te_tune_save": ([ctypes.c_char_p], _st),

@@ -42,6 +42,12 @@ def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
+def _local_offsets(plan):
+    off = np.empty(plan.n_pairs * plan.n_points + 1, np.int64)
+    check(lib().te_plan_local_offsets(plan._h, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+    return off
+
+
 def _problem(n_pairs, n_trials, n_samples, d_y, d_x, tau, u, k, window_start, window_len=None, trials=None,
              n_surrogates=0, window=0):
     """A te_problem and the arrays it points to (keep both alive while it is used)."""
@@ -142,6 +148,21 @@ class Plan:
         check(lib().te_estimate(self._h, _dev_ptr(x, torch.float32, "x"), _dev_ptr(y, torch.float32, "y"), wsp, wsn,
                                 sh, _dp(out)))
         return out
+
+    def local(self, x, y, ws=None, stream=None):
+        """Local TE of every pooled point (eq. 17-18): (list over (pair, point) of CUDA float64
+        arrays in window order, te float64 [P, C])."""
+        torch = _torch()
+        self._check_series(x, y)
+        off = _local_offsets(self)
+        lte = torch.empty(max(int(off[-1]), 1), dtype=torch.float64, device="cuda")
+        te_out = np.empty((self.n_pairs, self.n_points), np.float64)
+        wsp, wsn = self._ws_args(ws)
+        sh, _ = _stream_handle(stream)
+        check(lib().te_local(self._h, _dev_ptr(x, torch.float32, "x"), _dev_ptr(y, torch.float32, "y"), wsp, wsn, sh,
+                             ctypes.c_void_p(lte.data_ptr()), _dp(te_out)))
+        parts = [lte[off[g]:off[g + 1]] for g in range(self.n_pairs * self.n_points)]
+        return parts, te_out
 
     def surrogates(self, x, y, perms=None, ws=None, stream=None, use_graph=False):
         """Batched path: (te_orig [P, C], te_surr [P, C, S], p_value [P, C])."""

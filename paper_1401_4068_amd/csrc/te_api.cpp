@@ -174,7 +174,7 @@ static int history(const te_problem &p)
     return std::max(1 + (p.d_y - 1) * p.tau, p.u + (p.d_x - 1) * p.tau);
 }
 
-te_status Plan::build_group_batch(const std::vector<int> &groups, int n_surr, Batch *b) const
+te_status Plan::build_group_batch(const std::vector<int> &groups, int n_surr, Batch *b, bool local_outputs) const
 {
     // groups: indices g = pair * n_points + point; every group gets S+1 chunks
     // that share one (y_t', Y_past) block.
@@ -218,6 +218,10 @@ te_status Plan::build_group_batch(const std::vector<int> &groups, int n_surr, Ba
             d.ld = N;
             d.out = -1;
             d.perm = -1;
+            if (local_outputs && s == 0) {        // per-point outputs of the original, in window order
+                d.out = local_off[g];
+                d.perm = sig;
+            }
             d.n = N;
             d.result = gi * (n_surr + 1) + s;
             b->chunks.push_back(d);
@@ -315,7 +319,7 @@ int Plan::grid_waves(int64_t n_items) const
 // Enqueue one batch: upload tables, embed, search, reduce, p-values, copy results
 // into the pinned staging block `stage` (results, p-values, error word).
 te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, const int32_t *perms, char *ws,
-                              void *stage, hipStream_t st) const
+                              void *stage, hipStream_t st, double *lte_out) const
 {
     hipError_t e;
     char *tables_host = static_cast<char *>(stage);
@@ -355,6 +359,8 @@ te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, co
     a.eps_out = nullptr;
     a.cnt_out = nullptr;
     a.cnt_stride = 0;
+    a.lte_out = lte_out;
+    a.perm_base = sigma;
     a.sorted = sorted ? 1 : 0;
     if ((e = launch_search_timed(a, p.d_y, p.d_x, cfg, grid_waves(b.n_items), st)) != hipSuccess)
         return hip_fail(e, "search launch");
@@ -465,6 +471,10 @@ te_status te_plan_create(const te_problem *pr, te_plan *out)
         P.trials.push_back(Rc);
         P.npts.push_back(N);
     }
+    P.local_off.assign(1, 0);
+    for (int pr = 0; pr < p.n_pairs; ++pr)
+        for (int c = 0; c < p.n_points; ++c)
+            P.local_off.push_back(P.local_off.back() + P.npts[c]);
     P.p.window_start = nullptr;
     P.p.window_len = nullptr;
     P.p.trials = nullptr;
@@ -543,6 +553,28 @@ te_status te_surrogates(te_plan plan, const float *x, const float *y, const int3
         return s;
     return plan->impl.run_surrogates(x, y, perms, static_cast<char *>(ws), ws_bytes, (hipStream_t)hip_stream,
                                      use_graph != 0, te_orig, te_surr, p_value);
+}
+
+te_status te_plan_local_offsets(te_plan plan, int64_t *offsets)
+{
+    clear_error();
+    if (!plan || !offsets)
+        return fail(TE_ERR_INVALID, "null argument");
+    const auto &o = plan->impl.local_off;
+    std::copy(o.begin(), o.end(), offsets);
+    return TE_OK;
+}
+
+te_status te_local(te_plan plan, const float *x, const float *y, void *ws, size_t ws_bytes, void *hip_stream,
+                   double *lte, double *te_out)
+{
+    clear_error();
+    if (!plan || !x || !y || !ws || !lte)
+        return fail(TE_ERR_INVALID, "null argument");
+    te_status s = plan->impl.ensure_device();
+    if (s != TE_OK)
+        return s;
+    return plan->impl.run_local(x, y, static_cast<char *>(ws), ws_bytes, (hipStream_t)hip_stream, lte, te_out);
 }
 
 }  // extern "C"

@@ -196,6 +196,39 @@ te_status Plan::run_surrogates(const float *x, const float *y, const int32_t *pe
     return s;
 }
 
+// Local TE: the originals of every window in one batch, per-point terms written
+// through the sort maps to window order.
+te_status Plan::run_local(const float *x, const float *y, char *ws, size_t ws_bytes, hipStream_t st, double *lte,
+                          double *te_out) const
+{
+    const int G = p.n_pairs * p.n_points;
+    std::vector<int> all(G);
+    std::iota(all.begin(), all.end(), 0);
+    Batch b;
+    build_group_batch(all, 0, &b, true);
+    if (ws_bytes < b.total_bytes)
+        return fail(TE_ERR_NOMEM, "local TE needs a workspace of %zu bytes", b.total_bytes);
+    void *stg = pool.take(b.stage_bytes());
+    if (!stg)
+        return fail(TE_ERR_NOMEM, "pinned staging allocation failed");
+    te_status s = enqueue_batch(b, x, y, nullptr, ws, stg, st, lte);
+    hipError_t e = hipSuccess;
+    if (s == TE_OK && (e = hipStreamSynchronize(st)) != hipSuccess)
+        s = hip_fail(e, "hipStreamSynchronize");
+    bool bad = false;
+    std::vector<double> tmp(G);
+    if (s == TE_OK)
+        unpack_batch(b, stg, tmp.data(), nullptr, nullptr, &bad);
+    pool.give(stg);
+    if (s != TE_OK)
+        return s;
+    if (te_out)
+        std::copy(tmp.begin(), tmp.end(), te_out);
+    if (bad)
+        return fail(TE_ERR_INVALID, "non-finite input value");
+    return TE_OK;
+}
+
 // Plain path: each (pair, window) on its own -- embed, search, reduce -- in
 // window order on one stream; all estimates are copied back at the end.
 te_status Plan::estimate_plain(const float *x, const float *y, char *ws, size_t ws_bytes, hipStream_t st,

@@ -79,6 +79,7 @@ struct SearchArgs {
     int64_t cnt_stride;
     const int32_t *perm_base;   // sorted-to-original point maps (per-point outputs only)
     unsigned long long *work;   // optional: [0] += pairs evaluated in pass 1, [1] += in pass 2
+    double *lte_out;            // optional per-point local TE (at out + original index)
     int32_t sorted;             // chunks are sorted by the first target-past coordinate
     int32_t pad2_;
 };

@@ -441,6 +441,12 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                 atomicAdd(a.work + 1, evaluated2);
             }
         }
+        if (a.lte_out != nullptr && cd.out >= 0 && valid) {
+            int o = (cd.perm >= 0) ? a.perm_base[cd.perm + i] : i;
+            if (o < 0 || o >= n)
+                o = i;
+            a.lte_out[cd.out + o] = psi_of_count(k - 1) + term;
+        }
         if (a.eps_out != nullptr && cd.out >= 0 && valid) {
             // per-point outputs go to the point's index before sorting
             int o = (cd.perm >= 0) ? a.perm_base[cd.perm + i] : i;

@@ -82,6 +82,7 @@ struct Plan {
     bool sorted = true;                   // chunks sorted by the first target-past coordinate (TE_NO_SORT=1: off)
     std::vector<int32_t> wstart, wlen, trials;
     std::vector<int64_t> npts;
+    std::vector<int64_t> local_off;       // [n_pairs * n_points + 1] offsets of the local-TE output
     mutable std::mutex dev_mu;
     mutable bool dev_ready = false;
     mutable DeviceInfo dev;
@@ -96,10 +97,13 @@ struct Plan {
 
     ~Plan();
     te_status ensure_device() const;
-    te_status build_group_batch(const std::vector<int> &groups, int n_surr, Batch *b) const;
+    te_status build_group_batch(const std::vector<int> &groups, int n_surr, Batch *b,
+                                bool local_outputs = false) const;
     int grid_waves(int64_t n_items) const;
     te_status enqueue_batch(const Batch &b, const float *x, const float *y, const int32_t *perms, char *ws,
-                            void *stage, hipStream_t st) const;
+                            void *stage, hipStream_t st, double *lte_out = nullptr) const;
+    te_status run_local(const float *x, const float *y, char *ws, size_t ws_bytes, hipStream_t st, double *lte,
+                        double *te_out) const;
     te_status unpack_batch(const Batch &b, const void *stage, double *te_orig, double *te_surr, double *p_value,
                            bool *bad_input) const;
     te_status split_batches(size_t ws_bytes, std::vector<Batch> *out) const;

@@ -312,3 +312,27 @@ def test_work_counters_and_pruning(te):
     method = int(np.sum(n * (n - 1)))
     say("evaluated", w1, w2, "method", method)
     assert 0 < w1 <= method + int(np.sum(n)) and 0 < w2 <= method + int(np.sum(n))
+
+
+@pytest.mark.parametrize("no_sort", [False, True])
+def test_local_te_per_point(te, monkeypatch, no_sort):
+    """Per-point local TE (eq. 17 on the pooled points) against the oracle, point by point in
+    window order; its window means are the estimates (eq. 18)."""
+    if no_sort:
+        monkeypatch.setenv("TE_NO_SORT", "1")
+    wl = synth.uneven_surrogates(R=220, T=60, n_points=4, n_surrogates=0, n_lo=90, n_hi=2100)
+    say("local", no_sort, wl.chunk_sizes())
+    x, y, _ = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    parts, te_out = plan.local(x, y)
+    t0, _, _ = plan.surrogates(x, y)
+    np.testing.assert_array_equal(te_out, t0)
+    for p in range(wl.n_pairs):
+        for c in range(wl.n_points):
+            got = parts[p * wl.n_points + c].cpu().numpy()
+            pts = oracle.embed(wl.x[p], wl.y[p], wl.d_y, wl.d_x, wl.tau, wl.u, int(wl.window_start[c]),
+                               int(wl.window_len[c]), int(wl.trials[c]))
+            ref = oracle.local_te(pts, wl.d_y, wl.d_x, wl.k)
+            assert got.shape == ref.shape
+            np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12)
+            assert abs(got.mean() - te_out[p, c]) <= 1e-12

@@ -41,6 +41,10 @@ def test_hand_example_counts_and_te():
         assert e2.tolist() == case["eps"]
         assert c2.T.tolist() == case["counts_P_TP_PS"]
         assert tiny.te_exact_minus_gamma_free(c2, k) == case["te_nats"]
+        # per-point local values (eq. 17 on the pooled points) and their mean (eq. 18)
+        lte = oracle.local_te(pts, g["d_y"], g["d_x"], k)
+        assert lte.tolist() == pytest.approx(case["local_te_nats"], abs=1e-15)
+        assert lte.mean() == pytest.approx(case["te_nats"], abs=1e-15)
 
 
 # ------------------------------------------------------- exhaustive brute force
@@ -114,6 +118,30 @@ def test_te_from_counts_exact_rational():
     c[1] = np.minimum(c[1], c[0])
     c[2] = np.minimum(c[2], c[0])
     assert oracle.te_from_counts(c, k) == pytest.approx(float(tiny.te_exact_minus_gamma_free(c, k)), abs=1e-13)
+
+
+def test_local_te_exact_rational_and_mean():
+    key = derive_key(12)
+    N, k = 41, 3
+    c = np.floor(uniform01(key, 3 * N) * 25).reshape(3, N).astype(np.int32)
+    c[1] = np.minimum(c[1], c[0])
+    c[2] = np.minimum(c[2], c[0])
+    lte = oracle.local_from_counts(c, k)
+    for i in range(N):
+        exact = tiny.harmonic(k - 1) + tiny.harmonic(int(c[0, i])) - tiny.harmonic(int(c[1, i])) \
+            - tiny.harmonic(int(c[2, i]))
+        assert lte[i] == pytest.approx(float(exact), abs=1e-14)
+    # eq. 18: the average of the local values is the estimate of eq. 9
+    assert lte.mean() == pytest.approx(oracle.te_from_counts(c, k), abs=1e-13)
+
+
+def test_local_te_follows_point_permutation():
+    key = derive_key(13)
+    pts = normal64(key, 60 * 5).reshape(60, 5).astype(np.float32)
+    perm = permutation(derive_key(key, 1), 60)
+    a = oracle.local_te(pts, 2, 2, 4)
+    b = oracle.local_te(pts[perm], 2, 2, 4)
+    assert np.array_equal(a[perm], b)
 
 
 def test_p_value_convention():

@@ -131,7 +131,7 @@ te_status te_surrogates(te_plan plan, const float *x, const float *y, const int3
  *   lte_i = psi(k) + psi(n_P(i)+1) - psi(n_TP(i)+1) - psi(n_PS(i)+1),
  * the summand of eq. 9 with psi(k) included, so the mean over a window is its
  * estimate.  Same searches as te_estimate, all windows in one launch.
- *   lte      device float64 [te_plan_local_size] : window g = pair * n_points + point
+ *   lte      device float64 [off[n_pairs*n_points]] : window g = pair * n_points + point
  *            occupies [off[g], off[g+1]) with off from te_plan_local_offsets; points
  *            in window order q = r W_c + (t' - w_c)
  *   te_out   host float64 [n_pairs][n_points] (may be NULL)
@@ -139,6 +139,29 @@ te_status te_surrogates(te_plan plan, const float *x, const float *y, const int3
 te_status te_plan_local_offsets(te_plan plan, int64_t *offsets /* host [n_pairs*n_points + 1] */);
 te_status te_local(te_plan plan, const float *x, const float *y, void *ws, size_t ws_bytes,
                    void *hip_stream, double *lte, double *te_out);
+
+/* Delay reconstruction (eq. 5 and the delay scan that goes with it): the
+ * original estimate of every (pair, point) at each assumed source delay
+ * u_values[j] (the source past is taken at t-u, eq. 6-7), the delay with the
+ * largest estimate (the first in u_values order among equal maxima), and the
+ * trial-shuffle surrogate test (eq. 10) at that delay.  The plan's own u plays
+ * no part.  The maximizing delay is chosen on the device between the two
+ * searches; nothing returns to the host before the end.
+ *   u_values host int32 [n_u], 1 <= n_u <= 4096; each u >= 1 and every window
+ *            start >= u + (d_x - 1) tau (TE_ERR_INVALID otherwise)
+ *   perms    as te_surrogates (may be NULL when n_surrogates == 0)
+ *   ws       device workspace of ws_bytes >= the minimum given by
+ *            te_delay_scan_workspace_bytes (smaller workspaces are split into
+ *            several launches over window groups, with identical results)
+ *   te_scan  host float64 [n_pairs][n_points][n_u]
+ *   u_best   host int32 [n_pairs][n_points] (may be NULL)
+ *   te_surr  host float64 [n_pairs][n_points][n_surrogates] at u_best (NULL if S == 0)
+ *   p_value  host float64 [n_pairs][n_points] at u_best (NaN if S == 0; may be NULL) */
+te_status te_delay_scan_workspace_bytes(te_plan plan, const int32_t *u_values, int32_t n_u, size_t *full,
+                                        size_t *minimum);
+te_status te_delay_scan(te_plan plan, const float *x, const float *y, const int32_t *perms,
+                        const int32_t *u_values, int32_t n_u, void *ws, size_t ws_bytes, void *hip_stream,
+                        double *te_scan, int32_t *u_best, double *te_surr, double *p_value);
 
 /* Kernel-level export in the shape of the paper's neighbour-search call
  * ("Input data"; "Implementation interface"): several pre-embedded chunks

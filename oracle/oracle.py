@@ -197,6 +197,39 @@ def te_workload(wl, pairs=None, points=None, surrogates=None, n_threads=0, mode=
     return dict(zip(keys, te.tolist()))
 
 
+def delay_scan(wl, u_values, pairs=None, points=None, n_threads=0, mode=0):
+    """Delay reconstruction (eq. 5): the original TE at every assumed delay, the
+    maximizing delay (first maximum in u_values order), and the surrogate TE and
+    p-value (surrogate test of eq. 10) at that delay.
+
+    Returns dicts keyed by (pair, point): te_scan -> [n_u] array, u_best -> int,
+    te_surr -> [S] array, p_value -> float (NaN without surrogates).
+    """
+    u_values = [int(u) for u in u_values]
+    jobs, keys = workload_jobs(wl, pairs, points, surrogates=[0])
+    keys = [key[:2] for key in keys]
+    scan = np.empty((len(keys), len(u_values)))
+    for j, u in enumerate(u_values):
+        scan[:, j] = te_jobs(wl.x, wl.y, wl.d_y, wl.d_x, wl.tau, u, wl.k, jobs, wl.perms, n_threads, mode)
+    te_scan = {key: scan[i] for i, key in enumerate(keys)}
+    u_best = {key: u_values[int(np.argmax(scan[i]))] for i, key in enumerate(keys)}
+    S = wl.n_surrogates
+    te_surr, pv = {}, {}
+    for u in sorted(set(u_best.values())):
+        sel = [key for key in keys if u_best[key] == u]
+        sj, sk = [], []
+        for (p, c) in sel:
+            sub, subk = workload_jobs(wl, [p], [c], range(1, S + 1))
+            sj += sub
+            sk += subk
+        te = te_jobs(wl.x, wl.y, wl.d_y, wl.d_x, wl.tau, u, wl.k, sj, wl.perms, n_threads, mode) if sj else []
+        got = dict(zip(sk, list(te)))
+        for (p, c) in sel:
+            te_surr[(p, c)] = np.array([got[(p, c, s)] for s in range(1, S + 1)])
+            pv[(p, c)] = p_value(te_scan[(p, c)][u_values.index(u)], te_surr[(p, c)]) if S else float("nan")
+    return te_scan, u_best, te_surr, pv
+
+
 def timed_te_jobs(*args, **kw):
     t0 = time.perf_counter()
     te = te_jobs(*args, **kw)

@@ -71,6 +71,8 @@ SIGNATURES = {
     "te_serve_close": ([_vp], _st),
     "te_plan_local_offsets": ([_vp, ctypes.POINTER(_i64)], _st),
     "te_local": ([_vp, _vp, _vp, _vp, _sz, _vp, _vp, _dp], _st),
+    "te_delay_scan_workspace_bytes": ([_vp, _vp, _i32, _szp, _szp], _st),
+    "te_delay_scan": ([_vp, _vp, _vp, _vp, _vp, _i32, _vp, _sz, _vp, _dp, _vp, _dp, _dp], _st),
     "te_autotune": ([_i32, _i32, _i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                      ctypes.POINTER(_i32), _dp], _st),
     "te_tune_save": ([ctypes.c_char_p], _st),

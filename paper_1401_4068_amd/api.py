@@ -164,6 +164,34 @@ class Plan:
         parts = [lte[off[g]:off[g + 1]] for g in range(self.n_pairs * self.n_points)]
         return parts, te_out
 
+    def delay_scan_workspace_bytes(self, u_values):
+        u = np.ascontiguousarray(u_values, np.int32)
+        f, m = ctypes.c_size_t(), ctypes.c_size_t()
+        check(lib().te_delay_scan_workspace_bytes(self._h, ctypes.c_void_p(u.ctypes.data), len(u), ctypes.byref(f),
+                                                  ctypes.byref(m)))
+        return f.value, m.value
+
+    def delay_scan(self, x, y, u_values, perms=None, ws=None, stream=None):
+        """Delay reconstruction (eq. 5): (te_scan [P, C, n_u], u_best int32 [P, C],
+        te_surr [P, C, S] at u_best, p_value [P, C])."""
+        torch = _torch()
+        self._check_series(x, y)
+        u = np.ascontiguousarray(u_values, np.int32)
+        P, C, S = self.n_pairs, self.n_points, self.n_surrogates
+        if ws is None:
+            ws = torch.empty(int(self.delay_scan_workspace_bytes(u)[0]), dtype=torch.uint8, device="cuda")
+        te_scan = np.empty((P, C, len(u)), np.float64)
+        u_best = np.empty((P, C), np.int32)
+        te_surr = np.empty((P, C, S), np.float64) if S else None
+        pv = np.empty((P, C), np.float64)
+        pp = _dev_ptr(perms, torch.int32, "perms") if perms is not None else None
+        sh, _ = _stream_handle(stream)
+        check(lib().te_delay_scan(self._h, _dev_ptr(x, torch.float32, "x"), _dev_ptr(y, torch.float32, "y"), pp,
+                                  ctypes.c_void_p(u.ctypes.data), len(u), _dev_ptr(ws, torch.uint8, "ws"),
+                                  ws.numel(), sh, _dp(te_scan), ctypes.c_void_p(u_best.ctypes.data),
+                                  _dp(te_surr) if S else None, _dp(pv)))
+        return te_scan, u_best, te_surr, pv
+
     def surrogates(self, x, y, perms=None, ws=None, stream=None, use_graph=False):
         """Batched path: (te_orig [P, C], te_surr [P, C, S], p_value [P, C])."""
         torch = _torch()

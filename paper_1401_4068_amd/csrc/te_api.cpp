@@ -174,8 +174,10 @@ static int history(const te_problem &p)
     return std::max(1 + (p.d_y - 1) * p.tau, p.u + (p.d_x - 1) * p.tau);
 }
 
-te_status Plan::build_group_batch(const std::vector<int> &groups, int n_surr, Batch *b, bool local_outputs) const
+te_status Plan::build_group_batch(const std::vector<int> &groups, int n_surr, Batch *b, const BatchOptions &opt) const
 {
+    if (opt.delays)
+        n_surr = (int)opt.delays->size() - 1;
     // groups: indices g = pair * n_points + point; every group gets S+1 chunks
     // that share one (y_t', Y_past) block.
     b->n_groups = (int)groups.size();
@@ -218,7 +220,7 @@ te_status Plan::build_group_batch(const std::vector<int> &groups, int n_surr, Ba
             d.ld = N;
             d.out = -1;
             d.perm = -1;
-            if (local_outputs && s == 0) {        // per-point outputs of the original, in window order
+            if (opt.local_outputs && s == 0) {        // per-point outputs of the original, in window order
                 d.out = local_off[g];
                 d.perm = sig;
             }
@@ -230,7 +232,11 @@ te_status Plan::build_group_batch(const std::vector<int> &groups, int n_surr, Ba
             t.s = fl;
             t.perm = -1;
             t.sig = sig;
-            if (s > 0) {
+            if (opt.delays)
+                t.u = (*opt.delays)[s];
+            if (opt.delay_from_device)
+                t.u_slot = gi + 1;
+            if (s > 0 && !opt.delays) {
                 t.perm = (((int64_t)pair * p.n_points + c) * n_surr + (s - 1)) * p.n_trials;
                 b->perm_rows.push_back(t.perm);
                 b->perm_rc.push_back(trials[c]);
@@ -319,7 +325,7 @@ int Plan::grid_waves(int64_t n_items) const
 // Enqueue one batch: upload tables, embed, search, reduce, p-values, copy results
 // into the pinned staging block `stage` (results, p-values, error word).
 te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, const int32_t *perms, char *ws,
-                              void *stage, hipStream_t st, double *lte_out) const
+                              void *stage, hipStream_t st, double *lte_out, const int32_t *u_dev) const
 {
     hipError_t e;
     char *tables_host = static_cast<char *>(stage);
@@ -343,8 +349,8 @@ te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, co
                     reinterpret_cast<uint64_t *>(ws + b.off_scratch), p.n_trials, p.n_samples, st);
     if (e != hipSuccess)
         return hip_fail(e, "sort launch");
-    e = launch_embed(x, y, perms, sigma, reinterpret_cast<const EmbedTask *>(ws + b.off_tasks), (int)b.tasks.size(),
-                     base, p.n_trials, p.n_samples, p.d_y, p.d_x, p.tau, p.u, ctr + 1, st);
+    e = launch_embed(x, y, perms, sigma, u_dev, reinterpret_cast<const EmbedTask *>(ws + b.off_tasks),
+                     (int)b.tasks.size(), base, p.n_trials, p.n_samples, p.d_y, p.d_x, p.tau, p.u, ctr + 1, st);
     if (e != hipSuccess)
         return hip_fail(e, "embed launch");
     SearchArgs a{};

@@ -205,7 +205,9 @@ te_status Plan::run_local(const float *x, const float *y, char *ws, size_t ws_by
     std::vector<int> all(G);
     std::iota(all.begin(), all.end(), 0);
     Batch b;
-    build_group_batch(all, 0, &b, true);
+    BatchOptions opt;
+    opt.local_outputs = true;
+    build_group_batch(all, 0, &b, opt);
     if (ws_bytes < b.total_bytes)
         return fail(TE_ERR_NOMEM, "local TE needs a workspace of %zu bytes", b.total_bytes);
     void *stg = pool.take(b.stage_bytes());
@@ -332,8 +334,8 @@ te_status Plan::estimate_plain(const float *x, const float *y, char *ws, size_t 
             if (e != hipSuccess)
                 break;
         }
-        e = launch_embed(x, y, nullptr, sigma, dt + g, 1, base, p.n_trials, p.n_samples, p.d_y, p.d_x, p.tau, p.u,
-                         ctr + 4 * g + 1, st);
+        e = launch_embed(x, y, nullptr, sigma, nullptr, dt + g, 1, base, p.n_trials, p.n_samples, p.d_y, p.d_x,
+                         p.tau, p.u, ctr + 4 * g + 1, st);
         if (e != hipSuccess)
             break;
         SearchArgs a{};

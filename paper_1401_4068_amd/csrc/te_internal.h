@@ -41,6 +41,8 @@ struct EmbedTask {
     int64_t sig;      // int32 offset of the window's sorted-to-original point map, or -1 (identity)
     int32_t pair, w, W, Rc;
     int32_t n;        // Rc * W
+    int32_t u;        // source delay of this block; 0: the launch's delay
+    int32_t u_slot;   // > 0: the delay is read on the device from u_dev[u_slot - 1] (overrides u)
     int32_t pad_;
 };
 
@@ -100,7 +102,8 @@ struct DeviceInfo {
 // Kernel launchers (te_kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 hipError_t launch_embed(const float *x, const float *y, const int32_t *perms, const int32_t *sigma,
-                        const EmbedTask *tasks, int n_tasks, float *base, int R, int T, int d_y, int d_x, int tau,
+                        const int32_t *u_dev, const EmbedTask *tasks, int n_tasks, float *base, int R, int T,
+                        int d_y, int d_x, int tau,
                         int u, int32_t *err, hipStream_t st);
 hipError_t launch_sort(const float *y, const float *pts, const SortTask *tasks, int n_tasks, int32_t *sigma,
                        uint64_t *scratch, int R, int T, hipStream_t st);
@@ -113,6 +116,8 @@ hipError_t launch_search(const SearchArgs &a, int d_y, int d_x, const SearchConf
 hipError_t launch_reduce(const ChunkDesc *chunks, int n_chunks, const double *partial, int k,
                          const int32_t *err, double *results, hipStream_t st);
 hipError_t launch_pvalues(const double *results, int n_groups, int n_surr, double *pv, hipStream_t st);
+hipError_t launch_argmax_u(const double *results, int n_groups, int n_u, const int32_t *u_values, int32_t *u_sel,
+                           hipStream_t st);
 bool search_supported(int d_y, int d_x, int k, int slots);
 unsigned long long *work_counters();   // this device's evaluated-pair counters (measurement)
 

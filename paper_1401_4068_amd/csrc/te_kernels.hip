@@ -9,6 +9,7 @@
 //                    the per-point digamma terms of eq. 9 summed per work item.
 //   reduce_kernel    eq. 9/10 per chunk: psi(k) + mean of the terms.
 //   pvalue_kernel    fraction of surrogate estimates >= the original.
+//   argmax_u_kernel  eq. 5: the assumed delay with the largest estimate.
 //
 // The search kernel is persistent: every wavefront pulls work items (one
 // chunk, 64 consecutive reference points) from a global counter until the
@@ -485,11 +486,18 @@ __global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t n)
 
 __global__ void embed_kernel(const float *__restrict__ x, const float *__restrict__ y,
                              const int32_t *__restrict__ perms, const int32_t *__restrict__ sigma,
-                             const EmbedTask *__restrict__ tasks, float *__restrict__ base, int R, int T, int d_y,
-                             int d_x, int tau, int u, int32_t *err)
+                             const int32_t *__restrict__ u_dev, const EmbedTask *__restrict__ tasks,
+                             float *__restrict__ base, int R, int T, int d_y, int d_x, int tau, int u, int32_t *err)
 {
     const EmbedTask tk = tasks[blockIdx.x];
     const int n = tk.n;
+    // source delay of this block: the launch's, the task's own, or one chosen on the device
+    if (tk.u > 0)
+        u = tk.u;
+    if (tk.u_slot > 0 && u_dev != nullptr)
+        u = u_dev[tk.u_slot - 1];
+    // the host checks every delay against the window starts; keep reads in bounds regardless
+    const bool u_ok = u >= 1 && tk.w - u - (d_x - 1) * tau >= 0 && tk.w + tk.W - u <= T;
     const int64_t pr = (int64_t)tk.pair * R;
     bool bad = false;
     for (int q = threadIdx.x; q < n; q += blockDim.x) {
@@ -524,8 +532,9 @@ __global__ void embed_kernel(const float *__restrict__ x, const float *__restric
                 base[tk.tp + (int64_t)(1 + m) * n + q] = v;
             }
         }
+        bad |= !u_ok;
         for (int m = 0; m < d_x; ++m) {
-            const float v = xr[t - u - m * tau];
+            const float v = u_ok ? xr[t - u - m * tau] : 0.0f;
             bad |= !isfinite(v);
             base[tk.s + (int64_t)m * n + q] = v;
         }
@@ -760,6 +769,22 @@ __global__ void pvalue_kernel(const double *__restrict__ results, int n_groups, 
     pv[g] = n_surr > 0 ? (double)c / (double)n_surr : __builtin_nan("");
 }
 
+// Delay reconstruction (eq. 5): per window group, the delay whose original
+// estimate is largest (the first one in table order among equal maxima).
+__global__ void argmax_u_kernel(const double *__restrict__ results, int n_groups, int n_u,
+                                const int32_t *__restrict__ u_values, int32_t *__restrict__ u_sel)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_groups)
+        return;
+    const double *r = results + (int64_t)g * n_u;
+    int best = 0;
+    for (int j = 1; j < n_u; ++j)
+        if (r[j] > r[best])
+            best = j;
+    u_sel[g] = u_values[best];
+}
+
 // ------------------------------------------------------------- dispatch
 
 typedef void (*search_fn)(SearchArgs);
@@ -859,13 +884,23 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st)
 }
 
 hipError_t launch_embed(const float *x, const float *y, const int32_t *perms, const int32_t *sigma,
-                        const EmbedTask *tasks, int n_tasks, float *base, int R, int T, int d_y, int d_x, int tau,
-                        int u, int32_t *err, hipStream_t st)
+                        const int32_t *u_dev, const EmbedTask *tasks, int n_tasks, float *base, int R, int T,
+                        int d_y, int d_x, int tau, int u, int32_t *err, hipStream_t st)
 {
     if (n_tasks <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(embed_kernel, dim3(n_tasks), dim3(256), 0, st, x, y, perms, sigma, tasks, base, R, T, d_y,
-                       d_x, tau, u, err);
+    hipLaunchKernelGGL(embed_kernel, dim3(n_tasks), dim3(256), 0, st, x, y, perms, sigma, u_dev, tasks, base, R, T,
+                       d_y, d_x, tau, u, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_argmax_u(const double *results, int n_groups, int n_u, const int32_t *u_values, int32_t *u_sel,
+                           hipStream_t st)
+{
+    if (n_groups <= 0 || n_u <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(argmax_u_kernel, dim3((n_groups + 127) / 128), dim3(128), 0, st, results, n_groups, n_u,
+                       u_values, u_sel);
     return hipGetLastError();
 }
 

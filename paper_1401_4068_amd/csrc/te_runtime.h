@@ -77,6 +77,14 @@ struct GraphEntry {
     std::vector<void *> stages;
 };
 
+// Variants of a window group in one batch: by default the original and the
+// n_surr trial-shuffled surrogates.
+struct BatchOptions {
+    bool local_outputs = false;                   // per-point local TE of the originals
+    const std::vector<int32_t> *delays = nullptr; // variants: the original at each of these source delays
+    bool delay_from_device = false;               // source delay of group gi read from u_dev[gi]
+};
+
 struct Plan {
     te_problem p{};
     bool sorted = true;                   // chunks sorted by the first target-past coordinate (TE_NO_SORT=1: off)
@@ -98,10 +106,15 @@ struct Plan {
     ~Plan();
     te_status ensure_device() const;
     te_status build_group_batch(const std::vector<int> &groups, int n_surr, Batch *b,
-                                bool local_outputs = false) const;
+                                const BatchOptions &opt = BatchOptions()) const;
     int grid_waves(int64_t n_items) const;
     te_status enqueue_batch(const Batch &b, const float *x, const float *y, const int32_t *perms, char *ws,
-                            void *stage, hipStream_t st, double *lte_out = nullptr) const;
+                            void *stage, hipStream_t st, double *lte_out = nullptr,
+                            const int32_t *u_dev = nullptr) const;
+    size_t scan_bytes(const std::vector<int> &groups, const std::vector<int32_t> &delays) const;
+    te_status run_scan(const float *x, const float *y, const int32_t *perms, const std::vector<int32_t> &delays,
+                       char *ws, size_t ws_bytes, hipStream_t st, double *te_scan, int32_t *u_best,
+                       double *te_surr, double *p_value) const;
     te_status run_local(const float *x, const float *y, char *ws, size_t ws_bytes, hipStream_t st, double *lte,
                         double *te_out) const;
     te_status unpack_batch(const Batch &b, const void *stage, double *te_orig, double *te_surr, double *p_value,

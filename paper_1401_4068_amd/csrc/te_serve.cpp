@@ -319,7 +319,7 @@ bool Server::admit_one(Job *j)
                         reinterpret_cast<uint64_t *>(bat + b.off_scratch), P.p.n_trials, P.p.n_samples, setup_stream);
     if (e == hipSuccess)
         e = launch_embed(reinterpret_cast<const float *>(reg + j->off_x), reinterpret_cast<const float *>(reg + j->off_y),
-                         perm, sigma, reinterpret_cast<const EmbedTask *>(bat + b.off_tasks), (int)b.tasks.size(),
+                         perm, sigma, nullptr, reinterpret_cast<const EmbedTask *>(bat + b.off_tasks), (int)b.tasks.size(),
                          reinterpret_cast<float *>(bat + b.off_coords), P.p.n_trials, P.p.n_samples, P.p.d_y, P.p.d_x,
                          P.p.tau, P.p.u, ctr + 1, setup_stream);
     if (e == hipSuccess)

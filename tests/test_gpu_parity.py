@@ -336,3 +336,70 @@ def test_local_te_per_point(te, monkeypatch, no_sort):
             assert got.shape == ref.shape
             np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12)
             assert abs(got.mean() - te_out[p, c]) <= 1e-12
+
+
+def _scan_workload(n_surrogates=5):
+    return synth.generic((31, 7), n_pairs=2, R=120, T=80, d_y=2, d_x=2, u=3, starts=(20, 35, 50),
+                         windows=(10, 7, 15), trials=(120, 80, 100), n_surrogates=n_surrogates, coupling=0.6)
+
+
+def _check_scan(wl, u_values, got):
+    te_scan, u_best, te_surr, pv = got
+    ref_scan, ref_best, ref_surr, ref_pv = oracle.delay_scan(wl, u_values)
+    for (p, c), r in ref_scan.items():
+        assert np.max(np.abs(te_scan[p, c] - r)) <= TIGHT, (p, c)
+        top = np.sort(r)[::-1]
+        if len(top) > 1 and top[0] - top[1] < 1e-9:       # a near tie: either delay is a maximum
+            assert r[u_values.index(int(u_best[p, c]))] >= top[0] - 1e-9
+            continue
+        assert u_best[p, c] == ref_best[(p, c)], (p, c)
+        if wl.n_surrogates:
+            assert np.max(np.abs(te_surr[p, c] - ref_surr[(p, c)])) <= TIGHT, (p, c)
+            assert pv[p, c] == ref_pv[(p, c)]
+        else:
+            assert math.isnan(pv[p, c])
+
+
+def test_delay_scan_matches_oracle(te):
+    """eq. 5: originals at every delay, the device-side argmax, surrogates at the chosen delay."""
+    wl = _scan_workload()
+    u_values = [1, 2, 3, 4, 5, 6, 7, 8, 3]
+    x, y, perms = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    got = plan.delay_scan(x, y, u_values, perms)
+    say("scan", got[1].tolist())
+    _check_scan(wl, u_values, got)
+    np.testing.assert_array_equal(got[0][:, :, 2], got[0][:, :, 8])      # repeated delay, same estimate
+    # the scan at the plan's own delay equals te_surrogates
+    t0, ts, pv = plan.surrogates(x, y, perms)
+    np.testing.assert_array_equal(got[0][:, :, 2], t0)
+
+
+def test_delay_scan_split_workspace_and_no_surrogates(te):
+    import torch
+    wl = _scan_workload()
+    u_values = [2, 4, 6, 1, 3]
+    x, y, perms = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    full, minimum = plan.delay_scan_workspace_bytes(u_values)
+    assert full > minimum > 0
+    a = plan.delay_scan(x, y, u_values, perms)
+    ws = torch.empty(minimum, dtype=torch.uint8, device="cuda")
+    b = plan.delay_scan(x, y, u_values, perms, ws=ws)
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+    wl0 = _scan_workload(n_surrogates=0)
+    plan0 = te.Plan.from_workload(wl0)
+    got = plan0.delay_scan(x, y, u_values)
+    assert got[2] is None
+    _check_scan(wl0, u_values, got)
+
+
+def test_delay_scan_rejects_delays_without_history(te):
+    wl = _scan_workload()
+    x, y, perms = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    for bad in ([20], [0], []):
+        with pytest.raises(te.TEError) as ei:
+            plan.delay_scan(x, y, bad, perms)
+        assert ei.value.status == 1

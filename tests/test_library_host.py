@@ -103,3 +103,19 @@ def test_tuning_table_roundtrip(tmp_path):
     empty.write_text("garbage\n")
     with pytest.raises(te.TEError):
         te.tune_load(empty)
+
+
+def test_delay_scan_sizes_and_validation_without_gpu():
+    import paper_1401_4068_amd as te
+    _lib_or_build()
+    wl = synth.generic((31, 7), n_pairs=2, R=120, T=80, d_y=2, d_x=2, u=3, starts=(20, 35, 50),
+                       windows=(10, 7, 15), trials=(120, 80, 100), n_surrogates=5)
+    p = te.Plan.from_workload(wl)
+    full, minimum = p.delay_scan_workspace_bytes([1, 2, 3])
+    assert full > minimum > 0
+    # more delays need more room: one source block per delay
+    assert p.delay_scan_workspace_bytes(list(range(1, 10)))[0] > full
+    for bad, msg in (([20], "start at sample >= 21"), ([0], ">= 1"), ([], "n_u")):
+        with pytest.raises(te.TEError) as ei:
+            p.delay_scan_workspace_bytes(bad)
+        assert ei.value.status == 1 and msg in str(ei.value)

@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 import synth
-from closed_form import gaussian_mi, gaussian_te
+from closed_form import gaussian_mi, gaussian_te, gaussian_te_delay
 from oracle import oracle, tiny
 from synth.rng import derive_key, normal64, permutation, uniform01
 
@@ -322,3 +322,49 @@ def test_batched_oracle_equals_single_chunk_calls():
                            Rc=int(w.trials[c]), src_perm=perm)
         _, cnt = oracle.counts(pts, 2, 2, 4)
         assert v == oracle.te_from_counts(cnt, 4)
+
+
+# ------------------------------------------------------------ delay scan (eq. 5)
+
+def _delayed_pair(delay, coupling, R=200, T=60, start=30, window=10, d_y=2, d_x=1, n_surrogates=0, seed=77):
+    from synth.processes import coupled_ar
+    x, y = coupled_ar(synth.configs.BASE_SEED + seed, R, T, coupling=coupling, delay=delay)
+    wl = synth.configs.Workload(name="delayed", x=x[None], y=y[None], d_y=d_y, d_x=d_x, tau=1, u=1, k=4,
+                                window_start=np.array([start], np.int32), window_len=np.array([window], np.int32),
+                                trials=np.array([R], np.int32), n_surrogates=n_surrogates)
+    if n_surrogates:
+        wl.perms = synth.configs.make_perms(synth.configs.BASE_SEED + seed, 1, wl.trials, n_surrogates, R)
+    return wl
+
+
+def test_closed_form_delay_generalizes_the_var1_pin():
+    for c in (0.0, 0.4, 0.8):
+        assert gaussian_te_delay(c=c, delay=1, d_y=2, d_x=2) == pytest.approx(gaussian_te(c=c, d_y=2, d_x=2), abs=1e-14)
+    curve = [gaussian_te_delay(c=0.8, delay=4, d_y=2, d_x=1, u=u) for u in range(1, 9)]
+    assert int(np.argmax(curve)) + 1 == 4
+    # a source embedding of d_x samples sees x_{t-delay} for every u in [delay - d_x + 1, delay]
+    flat = [gaussian_te_delay(c=0.8, delay=4, d_y=2, d_x=2, u=u) for u in (3, 4)]
+    assert flat[0] == pytest.approx(flat[1], rel=1e-9)
+
+
+def test_delay_scan_recovers_the_coupling_delay():
+    """eq. 5: the scan's maximum sits at the true delay, and the curve follows the closed form."""
+    wl = _delayed_pair(delay=4, coupling=0.8)
+    u_values = list(range(1, 9))
+    te_scan, u_best, _, pv = oracle.delay_scan(wl, u_values)
+    assert u_best[(0, 0)] == 4
+    truth = np.array([gaussian_te_delay(c=0.8, delay=4, d_y=2, d_x=1, u=u) for u in u_values])
+    assert np.max(np.abs(te_scan[(0, 0)] - truth)) < 0.04
+    assert math.isnan(pv[(0, 0)])
+
+
+def test_delay_scan_ties_and_surrogates_at_the_chosen_delay():
+    wl = _delayed_pair(delay=3, coupling=0.8, n_surrogates=9, seed=78)
+    te_scan, u_best, te_surr, pv = oracle.delay_scan(wl, [5, 3, 3, 2])
+    assert u_best[(0, 0)] == 3                       # first maximum in table order
+    assert te_scan[(0, 0)][1] == te_scan[(0, 0)][2]
+    # the surrogates are those of eq. 10 at u = 3, and the p-value counts them
+    direct = oracle.te_jobs(wl.x, wl.y, wl.d_y, wl.d_x, wl.tau, 3, wl.k,
+                            [(0, 30, 10, 200, s) for s in range(9)], wl.perms)
+    np.testing.assert_array_equal(te_surr[(0, 0)], direct)
+    assert pv[(0, 0)] == 0.0

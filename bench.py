@@ -221,6 +221,109 @@ def batched_record(args, wl, wname):
     return rec
 
 
+def scan_record(args, scenario):
+    """Delay reconstruction over an AR coupling scenario (eq. 5, eq. 12-16): one step is
+    te_delay_scan over both directions, every window and every assumed delay, then the
+    surrogate test at the chosen delays.  Estimates per step: P C n_u originals plus
+    P C (S + 1) at the chosen delays."""
+    import torch
+    import synth
+    import paper_1401_4068_amd as te
+
+    wl = synth.ar_scenarios(scenario)
+    u_values = wl.meta["u_values"]
+    n_u = len(u_values)
+    D = wl.dim
+    N = int(wl.chunk_sizes()[0])
+    G = wl.n_pairs * wl.n_points
+    est = G * n_u + G * (wl.n_surrogates + 1)
+    pairs_per_step = est * N * (N - 1)
+    x = torch.from_numpy(wl.x).cuda()
+    y = torch.from_numpy(wl.y).cuda()
+    perms = torch.from_numpy(wl.perms).cuda()
+    tuned = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        tuned = te.autotune(wl.d_y, wl.d_x, wl.k, N)
+        tuned["tuning_s"] = round(time.perf_counter() - t0, 3)
+    plan = te.Plan.from_workload(wl)
+    full, _ = plan.delay_scan_workspace_bytes(u_values)
+    ws = torch.empty(full, dtype=torch.uint8, device="cuda")
+    step = lambda: plan.delay_scan(x, y, u_values, perms, ws=ws)                 # noqa: E731
+    for _ in range(args.warmup):
+        step()
+    te.profile_enable(True)
+    te.profile_read(reset=True)
+    te.profile_work(reset=True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        out = step()
+        lat.append(time.perf_counter() - s0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    k_ms, k_n = te.profile_read(reset=True)
+    w1, w2 = te.profile_work(reset=True)
+    te.profile_enable(False)
+    roof = None
+    if k_n > 0:
+        # two search launches per step (all delays; the chosen delay's test): their mean
+        avg_s = k_ms / k_n / 1e3
+        ops = (w1 * 2 * D + w2 * (2 * D + 2)) / k_n
+        achieved = ops / avg_s / 1e12
+        roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_OPS, unit="TFLOP/s",
+                    frac=round(achieved / PEAK_FP32_OPS, 4), traffic=None, avg_launch_ms=round(avg_s * 1e3, 4),
+                    launches=k_n, pairs_evaluated_per_launch=[int(w1 / k_n), int(w2 / k_n)],
+                    method_pairs_per_launch=int(pairs_per_step * args.steps / k_n))
+    te_scan, u_best, _, pv = out
+    findings = []
+    for p in range(wl.n_pairs):
+        for c in range(wl.n_points):
+            w0 = int(wl.window_start[c])
+            findings.append(dict(direction=wl.meta["directions"][p], window=[w0, w0 + int(wl.window_len[c])],
+                                 u_best=int(u_best[p, c]), te_max=round(float(te_scan[p, c].max()), 4),
+                                 p_value=float(pv[p, c])))
+    rec = dict(
+        metric=METRIC, value=round(est * args.steps / dt, 2), unit="estimates/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(dt / args.steps * 1e3, 4), higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f32", data="synthetic",
+        config=dict(workload="ar_scenario%d_delay_scan" % scenario, pairs=wl.n_pairs, trials=wl.n_trials,
+                    samples=wl.n_samples, windows=wl.n_points, points_per_window=N, d_y=wl.d_y, d_x=wl.d_x,
+                    tau=wl.tau, u_values=[u_values[0], u_values[-1]], dim=D, k=wl.k, surrogates=wl.n_surrogates,
+                    estimates_per_step=est, workspace_bytes=int(full), path="te_delay_scan"),
+        distance_evals_per_s=round(2 * pairs_per_step * args.steps / dt, 1),
+        latency_s=dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99))),
+        tuned_shape=tuned, roofline=roof, findings=findings)
+    if not args.no_cpu:
+        rec["cpu_baseline"] = scan_cpu_baseline(wl, u_values, est)
+    return rec
+
+
+def scan_cpu_baseline(wl, u_values, est_per_step, budget_s: float = 12.0):
+    """The oracle on a seeded sample of (direction, window, delay) originals, scaled by pairs."""
+    from oracle import oracle
+    from synth.rng import derive_key, permutation
+    threads = host_threads()
+    jobs = [(p, c, u) for p in range(wl.n_pairs) for c in range(wl.n_points) for u in u_values]
+    order = permutation(derive_key(4068, len(jobs)), len(jobs))
+    N = int(wl.chunk_sizes()[0])
+    done, t_total = 0, 0.0
+    while done < len(jobs) and t_total < budget_s:
+        sel = [jobs[i] for i in order[done:done + threads]]
+        t0 = time.perf_counter()
+        for u in sorted(set(j[2] for j in sel)):
+            js = [(p, int(wl.window_start[c]), int(wl.window_len[c]), int(wl.trials[c]), -1)
+                  for (p, c, uu) in sel if uu == u]
+            oracle.te_jobs(wl.x, wl.y, wl.d_y, wl.d_x, wl.tau, u, wl.k, js, wl.perms, n_threads=threads)
+        t_total += time.perf_counter() - t0
+        done += len(sel)
+    return dict(value=done / t_total, unit="estimates/s", cores=threads, kind="oracle",
+                sample="%d of %d original (direction, window, delay) chunks of N = %d, %.1f s wall on %d threads; "
+                       "every estimate of the step has the same N" % (done, len(jobs), N, t_total, threads))
+
+
 def served_record(args):
     """Poisson-arriving jobs through te_serve_* (continuous batching) and the same trace
     through te_surrogates one job at a time (FIFO)."""
@@ -309,7 +412,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="nonlinear", choices=["nonlinear", "linear", "uneven", "meg", "served"])
+    ap.add_argument("--workload", default="nonlinear",
+                    choices=["nonlinear", "linear", "uneven", "meg", "served", "ar1", "ar2", "ar3"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--graph", action="store_true", help="replay the batched step as a hipGraph")
@@ -338,6 +442,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "served":
         rec = served_record(args)
+    elif args.workload.startswith("ar"):
+        rec = scan_record(args, int(args.workload[2:]))
     else:
         wl, wname = make_workload(args.workload)
         rec = batched_record(args, wl, wname)

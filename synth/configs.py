@@ -19,7 +19,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .processes import coupled_ar, switched_pink_pair
+from .processes import ar_scenario, coupled_ar, switched_pink_pair
 from .rng import derive_key, permutations, uniform01
 
 BASE_SEED = 14014068
@@ -195,6 +195,30 @@ def generic(seed_ids, *, n_pairs=1, R=40, T=60, d_y=2, d_x=2, tau=1, u=1, k=4, s
                  n_surrogates=n_surrogates)
     if n_surrogates:
         w.perms = make_perms(int(derive_key(*seed_ids) % np.uint64(1 << 31)), n_pairs, tr, n_surrogates, R)
+    return w
+
+
+def ar_scenarios(scenario=1, R=50, T=3000, window=300, n_surrogates=500, d_y=2, d_x=1, k=4, n_points=None,
+                 name=None):
+    """AR(1) coupling scenarios (Table 1, eq. 12-16): 50 trials x 3000 samples, windows of 300
+    samples from sample 200 on (4 windows for scenario 1, 8 for scenarios 2 and 3), both
+    directions as two pairs (pair 0: X -> Y, pair 1: Y -> X), assumed delays u = 1..20
+    (1..30 for scenario 3) in meta["u_values"], trial-shuffled surrogates.
+    """
+    seed = BASE_SEED + 1000 * 6 + scenario
+    x, y = ar_scenario(seed, R, T, scenario)
+    C = 4 if scenario == 1 else 8
+    if n_points is not None:
+        C = n_points
+    starts = np.array([200 + window * c for c in range(C)], np.int32)
+    u_max = 30 if scenario == 3 else 20
+    w = Workload(name=name or f"ar_scenario{scenario}", x=np.stack([x, y]), y=np.stack([y, x]), d_y=d_y,
+                 d_x=d_x, tau=1, u=1, k=k, window_start=starts, window_len=np.full(C, window, np.int32),
+                 trials=np.full(C, R, np.int32), n_surrogates=n_surrogates,
+                 meta=dict(seed=seed, scenario=scenario, u_values=list(range(1, u_max + 1)),
+                           directions=["X->Y", "Y->X"]))
+    if n_surrogates:
+        w.perms = make_perms(seed, 2, w.trials, n_surrogates, R)
     return w
 
 

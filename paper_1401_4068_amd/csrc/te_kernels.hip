@@ -258,8 +258,7 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
             }
         };
         // four consecutive candidates j..j+3 (scalar loads, one per coordinate)
-        auto visit4 = [&](int j) {
-            float c[4][D];
+        auto load4 = [&](int j, float (&c)[4][D]) {
 #pragma unroll
             for (int m = 0; m < D; ++m) {
                 const f4v v = uload4(cp.p[m] + j);
@@ -268,6 +267,10 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                 c[2][m] = v.z;
                 c[3][m] = v.w;
             }
+        };
+        auto visit4 = [&](int j) {
+            float c[4][D];
+            load4(j, c);
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 visit(c[u]);
@@ -282,9 +285,6 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
         // In a chunk sorted by the first target-past coordinate p0, the joint
         // distance to candidate j is at least |fl32(p0_i - p0_j)|, which grows
         // monotonically away from the reference block (rounding is monotone).
-        // Once no lane can still improve at the nearest remaining candidate of a
-        // direction, no later candidate in that direction can either.
-        auto may_improve = [&](int j) { return ballot(absdiff(ref[1], uload(cp.p[1] + j)) < cur()) != 0; };
 
         int visited = n;                                  // candidates examined in pass 1
         if (!SORTED) {
@@ -294,44 +294,52 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
             for (; j < n; ++j)
                 visit1(j);
         } else {
-            int fwd_end = n, bwd_end = 0;
             const int e0 = min(n, r0 + kWave);
             int j = r0;                                   // the block's own points first
             for (; j + 4 <= e0; j += 4)
                 visit4(j);
             for (; j < e0; ++j)
                 visit1(j);
-            for (j = e0; j + 4 <= n; j += 4) {            // forward: p0 increasing
-                if (!may_improve(j)) {
-                    fwd_end = j;
-                    j = n + 1;
-                    break;
-                }
-                visit4(j);
+            // then outward: forward (p0 increasing), then backward, a group of four
+            // at a time.  After each group, its candidate farthest from the block
+            // is tested: if no lane could still use it, no later candidate of that
+            // direction could either (so the next group is not loaded).  All loads
+            // of a group feed its distances unconditionally: one wait per group.
+            int f = e0;
+            bool go = f < n;
+            while (go && f + 4 <= n) {
+                float c[4][D];
+                load4(f, c);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    visit(c[u]);
+                f += 4;
+                go = f < n && ballot(absdiff(ref[1], c[3][1]) < cur()) != 0;
             }
-            for (; j < n; ++j) {
-                if (!may_improve(j)) {
-                    fwd_end = j;
-                    break;
-                }
-                visit1(j);
+            while (go && f < n) {
+                const float p0 = uload(cp.p[1] + f);
+                visit1(f);
+                ++f;
+                go = f < n && ballot(absdiff(ref[1], p0) < cur()) != 0;
             }
-            for (j = r0; j >= 4; j -= 4) {                // backward: p0 decreasing
-                if (!may_improve(j - 1)) {
-                    bwd_end = j;
-                    j = -1;
-                    break;
-                }
-                visit4(j - 4);
+            int b = r0;
+            go = b > 0;
+            while (go && b >= 4) {
+                float c[4][D];
+                load4(b - 4, c);
+#pragma unroll
+                for (int u = 3; u >= 0; --u)
+                    visit(c[u]);
+                b -= 4;
+                go = b > 0 && ballot(absdiff(ref[1], c[0][1]) < cur()) != 0;
             }
-            for (; j > 0; --j) {
-                if (!may_improve(j - 1)) {
-                    bwd_end = j;
-                    break;
-                }
-                visit1(j - 1);
+            while (go && b > 0) {
+                const float p0 = uload(cp.p[1] + b - 1);
+                visit1(b - 1);
+                --b;
+                go = b > 0 && ballot(absdiff(ref[1], p0) < cur()) != 0;
             }
-            visited = fwd_end - bwd_end;
+            visited = f - b;
         }
         // k+1-th smallest including self (distance 0) = k-th neighbour without self
         const float eps = cur();

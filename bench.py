@@ -118,16 +118,15 @@ def batched_record(args, wl, wname):
     x = torch.from_numpy(wl.x).cuda()
     y = torch.from_numpy(wl.y).cuda()
     perms = torch.from_numpy(wl.perms).cuda() if wl.n_surrogates else None
-    tuned = None
-    if not args.no_tune:
-        # launch shape for the workload's median chunk size, tuned before anything is timed
-        t0 = time.perf_counter()
-        nmed = int(np.median(n))
-        tuned = te.autotune(wl.d_y, wl.d_x, wl.k, nmed)
-        tuned["tuning_s"] = round(time.perf_counter() - t0, 3)
     plan = te.Plan.from_workload(wl)
     full, minimum, plain_bytes = plan.workspace_bytes()
     ws = plan.workspace()
+    tuned = None
+    if not args.no_tune:
+        # launch shape tuned on the plan's own data before anything is timed
+        t0 = time.perf_counter()
+        tuned = plan.autotune(x, y, perms, ws=ws)
+        tuned["tuning_s"] = round(time.perf_counter() - t0, 3)
     stream = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
 
     def step():
@@ -167,7 +166,7 @@ def batched_record(args, wl, wname):
                     frac=round(achieved / PEAK_FP32_OPS, 4),
                     traffic=kernel_traffic() if wname == "nonlinear_ar_ensemble" else None,
                     kernel="search_kernel<%d,%d,k=%d,slots=%d,sorted>" % (wl.d_y, wl.d_x, wl.k,
-                                                                          tuned["slots"] if tuned else 8),
+                                                                          tuned["slots"] if tuned else 4),
                     avg_launch_ms=round(avg_s * 1e3, 4), launches=k_n, ops_per_launch=int(ops),
                     pairs_evaluated_per_launch=[int(p1), int(p2)],
                     method_pairs_per_launch=int(pairs_per_pass * args.steps / k_n),
@@ -241,12 +240,12 @@ def scan_record(args, scenario):
     x = torch.from_numpy(wl.x).cuda()
     y = torch.from_numpy(wl.y).cuda()
     perms = torch.from_numpy(wl.perms).cuda()
+    plan = te.Plan.from_workload(wl)
     tuned = None
     if not args.no_tune:
         t0 = time.perf_counter()
-        tuned = te.autotune(wl.d_y, wl.d_x, wl.k, N)
+        tuned = plan.autotune(x, y, perms)
         tuned["tuning_s"] = round(time.perf_counter() - t0, 3)
-    plan = te.Plan.from_workload(wl)
     full, _ = plan.delay_scan_workspace_bytes(u_values)
     ws = torch.empty(full, dtype=torch.uint8, device="cuda")
     step = lambda: plan.delay_scan(x, y, u_values, perms, ws=ws)                 # noqa: E731

@@ -256,6 +256,14 @@ te_status te_serve_close(te_server srv);
 te_status te_autotune(int32_t d_y, int32_t d_x, int32_t k, int32_t n_points, int32_t n_chunks,
                       void *ws, size_t ws_bytes, void *hip_stream,
                       int32_t *slots, int32_t *waves_per_wg, int32_t *wg_per_cu, double *best_ms);
+/* Tuning on the plan's own data (x, y, perms as for te_surrogates; ws of
+ * ws_bytes >= the plan's minimum workspace): every shape te_autotune tries is
+ * timed on a batch of the plan's largest window groups; the fastest becomes the
+ * plan's launch shape and is recorded in the table.  Results of the plan do not
+ * depend on the shape. */
+te_status te_plan_autotune(te_plan plan, const float *x, const float *y, const int32_t *perms, void *ws,
+                           size_t ws_bytes, void *hip_stream, int32_t *slots, int32_t *waves_per_wg,
+                           int32_t *wg_per_cu, double *ms);
 te_status te_tune_save(const char *path);
 te_status te_tune_load(const char *path);
 te_status te_tune_clear(void);

@@ -75,6 +75,8 @@ SIGNATURES = {
     "te_delay_scan": ([_vp, _vp, _vp, _vp, _vp, _i32, _vp, _sz, _vp, _dp, _vp, _dp, _dp], _st),
     "te_autotune": ([_i32, _i32, _i32, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                      ctypes.POINTER(_i32), _dp], _st),
+    "te_plan_autotune": ([_vp, _vp, _vp, _vp, _vp, _sz, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                          ctypes.POINTER(_i32), _dp], _st),
     "te_tune_save": ([ctypes.c_char_p], _st),
     "te_tune_load": ([ctypes.c_char_p], _st),
     "te_tune_clear": ([], _st),

@@ -111,6 +111,20 @@ class Plan:
         except Exception:
             pass
 
+    def autotune(self, x, y, perms=None, ws=None, stream=None):
+        """Pick the search kernel's launch shape on this plan's own data (te_plan_autotune)."""
+        torch = _torch()
+        self._check_series(x, y)
+        sl, wpg, wg = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        ms = ctypes.c_double()
+        pp = _dev_ptr(perms, torch.int32, "perms") if perms is not None else None
+        wsp, wsn = self._ws_args(ws)
+        sh, _ = _stream_handle(stream)
+        check(lib().te_plan_autotune(self._h, _dev_ptr(x, torch.float32, "x"), _dev_ptr(y, torch.float32, "y"), pp,
+                                     wsp, wsn, sh, ctypes.byref(sl), ctypes.byref(wpg), ctypes.byref(wg),
+                                     ctypes.byref(ms)))
+        return dict(slots=sl.value, waves_per_wg=wpg.value, wg_per_cu=wg.value, ms=ms.value)
+
     def workspace_bytes(self):
         f, m, p = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
         check(lib().te_plan_workspace_bytes(self._h, ctypes.byref(f), ctypes.byref(m), ctypes.byref(p)))

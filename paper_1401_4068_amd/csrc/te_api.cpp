@@ -106,6 +106,29 @@ void Batch::finish_layout()
     }
     chunks.swap(sorted);
 
+    // XCD work queues: contiguous item ranges of equal estimated work (an
+    // item of a chunk of n points costs about n), in the longest-first order
+    part_start.assign(kQueues + 1, 0);
+    {
+        double total = 0.0;
+        for (const ChunkDesc &d : chunks)
+            total += (double)d.n * ((d.n + kWave - 1) / kWave);
+        double acc = 0.0;
+        int p = 1;
+        for (const ChunkDesc &d : chunks) {
+            const int nb = (d.n + kWave - 1) / kWave;
+            for (int bk = 0; bk < nb; ++bk) {
+                acc += d.n;
+                while (p < kQueues && acc >= total * p / kQueues)
+                    part_start[p++] = d.item0 + bk + 1;
+            }
+        }
+        while (p <= kQueues)
+            part_start[p++] = (int32_t)n_items;
+        for (int q = 1; q <= kQueues; ++q)
+            part_start[q] = std::max(part_start[q], part_start[q - 1]);
+    }
+
     size_t o = 0;
     off_coords = o;
     o = align_up(o + sizeof(float) * (size_t)n_floats, 256);
@@ -122,6 +145,8 @@ void Batch::finish_layout()
     o = align_up(o + sizeof(int32_t) * perm_rc.size(), 16);
     off_sorts = o;
     o = align_up(o + sizeof(SortTask) * sorts.size(), 16);
+    off_parts = o;
+    o = align_up(o + sizeof(int32_t) * part_start.size(), 16);
     tables_bytes = o - off_tables;
     off_partial = align_up(o, 256);
     o = off_partial + sizeof(double) * (size_t)std::max<int64_t>(n_items, 1);
@@ -131,6 +156,8 @@ void Batch::finish_layout()
     o = off_pv + sizeof(double) * (size_t)std::max(n_groups, 1);
     off_ctr = align_up(o, 256);
     o = off_ctr + sizeof(int32_t) * 4;
+    off_qctr = align_up(o, 64);
+    o = off_qctr + sizeof(int32_t) * kQueues;
     off_sigma = align_up(o, 256);
     o = off_sigma + sizeof(int32_t) * (size_t)n_sigma;
     off_scratch = align_up(o, 256);
@@ -150,6 +177,7 @@ void Batch::finish_layout()
     }
     if (!sorts.empty())
         std::memcpy(host_tables.data() + (off_sorts - off_tables), sorts.data(), sizeof(SortTask) * sorts.size());
+    std::memcpy(host_tables.data() + (off_parts - off_tables), part_start.data(), sizeof(int32_t) * part_start.size());
 }
 
 bool sorting_enabled()
@@ -336,6 +364,9 @@ te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, co
     int32_t *ctr = reinterpret_cast<int32_t *>(ws + b.off_ctr);
     if ((e = launch_fill_i32(ctr, 0, 4, st)) != hipSuccess)
         return hip_fail(e, "fill");
+    int32_t *qctr = reinterpret_cast<int32_t *>(ws + b.off_qctr);
+    if ((e = launch_fill_i32(qctr, 0, kQueues, st)) != hipSuccess)
+        return hip_fail(e, "fill");
     float *base = reinterpret_cast<float *>(ws + b.off_coords);
     if (!b.perm_rows.empty()) {
         e = launch_check_perms(perms, reinterpret_cast<const int64_t *>(ws + b.off_prow),
@@ -360,7 +391,9 @@ te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, co
     a.n_chunks = (int32_t)b.chunks.size();
     a.n_items = (int32_t)b.n_items;
     a.k = p.k;
-    a.counter = ctr;
+    a.counter = qctr;
+    a.n_parts = kQueues;
+    a.part_start = reinterpret_cast<const int32_t *>(ws + b.off_parts);
     a.partial = reinterpret_cast<double *>(ws + b.off_partial);
     a.eps_out = nullptr;
     a.cnt_out = nullptr;

@@ -29,7 +29,8 @@ bool tuned_config(int d_y, int d_x, int k, int64_t n, SearchConfig *out);
 
 // Launch shape of the search kernel for chunks of about n points: the autotuner's
 // table entry when there is one (TE_TUNE_FILE names a table loaded on first use),
-// else 8 slots, 4 waves per workgroup and full occupancy.  TE_SLOTS,
+// else 4 slots, 4 waves per workgroup and full occupancy (the fastest shape measured
+// on the nonlinear-ensemble and MEG-like workloads).  TE_SLOTS,
 // TE_WAVES_PER_WG and TE_WG_PER_CU override single fields (measurements).
 SearchConfig default_config(const DeviceInfo &dev, int d_y, int d_x, int k, int64_t n)
 {
@@ -40,13 +41,13 @@ SearchConfig default_config(const DeviceInfo &dev, int d_y, int d_x, int k, int6
         if (f && *f)
             te_tune_load(f);
     });
-    SearchConfig c{8, 4, 0};
+    SearchConfig c{4, 4, 0};
     SearchConfig t;
     if (tuned_config(d_y, d_x, k, n, &t))
         c = t;
     c.slots = env_int("TE_SLOTS", c.slots);
     if (c.slots != 4 && c.slots != 8 && c.slots != 16)
-        c.slots = 8;
+        c.slots = 4;
     c.waves_per_wg = std::min(kMaxWavesPerWG, std::max(1, env_int("TE_WAVES_PER_WG", c.waves_per_wg)));
     const int occ = search_occupancy(d_y, d_x, k, c.slots, c.waves_per_wg);
     if (c.wg_per_cu <= 0 || c.wg_per_cu > std::max(1, occ))

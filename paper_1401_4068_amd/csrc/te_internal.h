@@ -83,8 +83,15 @@ struct SearchArgs {
     unsigned long long *work;   // optional: [0] += pairs evaluated in pass 1, [1] += in pass 2
     double *lte_out;            // optional per-point local TE (at out + original index)
     int32_t sorted;             // chunks are sorted by the first target-past coordinate
-    int32_t pad2_;
+    int32_t n_parts;            // > 1: items split into n_parts queues (counter[p] heads queue p), see kQueues
+    const int32_t *part_start;  // [n_parts + 1] first item of each queue (n_parts > 1)
 };
+
+// Work queues of a batched search: one per XCD of an MI355X.  Workgroups are
+// dispatched to the XCDs round-robin, so the waves of workgroup g start on queue
+// g % kQueues and a chunk's coordinates stay in one XCD's L2; a wave whose queue
+// is empty moves on to the next one.
+constexpr int kQueues = 8;
 
 // Tunable launch shape of the search kernel.
 struct SearchConfig {

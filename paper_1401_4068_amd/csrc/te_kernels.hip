@@ -203,14 +203,26 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
     const int lane = threadIdx.x & (kWave - 1);
     const int k = GENERIC ? a.k : KP1 - 1;
 
+    const int nq = a.n_parts > 1 ? a.n_parts : 1;
+    int qp = (int)(blockIdx.x % (unsigned)nq);   // this wave's queue
+    int drained = 0;                              // queues found empty so far
     for (;;) {
         // ---- claim the next work item (wave-uniform)
         int q = 0;
         if (lane == 0)
-            q = atomicAdd(a.counter, 1);
+            q = atomicAdd(a.counter + qp, 1);
         q = __builtin_amdgcn_readlane(q, 0);
-        if (q >= a.n_items)
+        if (nq > 1) {
+            q += uload_i(a.part_start + qp);
+            if (q >= uload_i(a.part_start + qp + 1)) {
+                if (++drained >= nq)
+                    break;
+                qp = qp + 1 == nq ? 0 : qp + 1;
+                continue;
+            }
+        } else if (q >= a.n_items) {
             break;
+        }
         const int ci = find_chunk(a.item_start, a.n_chunks, q);
         ChunkDesc cd;
         {

@@ -265,6 +265,120 @@ te_status te_autotune(int32_t d_y, int32_t d_x, int32_t k, int32_t n_points, int
     return TE_OK;
 }
 
+// Tuning on a plan's own data: the shapes of te_autotune, each timed on a batch
+// of the plan's largest window groups (originals and surrogates, longest first)
+// holding at least four items per resident wave of the widest shape, or as many
+// groups as the workspace takes.  The fastest shape becomes the plan's and is
+// recorded in the table under the plan's median chunk size.
+te_status te_plan_autotune(te_plan plan, const float *x, const float *y, const int32_t *perms, void *ws_,
+                           size_t ws_bytes, void *hip_stream, int32_t *slots, int32_t *waves_per_wg,
+                           int32_t *wg_per_cu, double *best_ms)
+{
+    clear_error();
+    if (!plan || !x || !y || !ws_)
+        return fail(TE_ERR_INVALID, "null argument");
+    const Plan &P = plan->impl;
+    if (P.p.n_surrogates > 0 && !perms)
+        return fail(TE_ERR_INVALID, "n_surrogates > 0 needs perms");
+    te_status s = P.ensure_device();
+    if (s != TE_OK)
+        return s;
+    char *ws = static_cast<char *>(ws_);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int G = P.p.n_pairs * P.p.n_points;
+    std::vector<int> order(G);
+    for (int g = 0; g < G; ++g)
+        order[g] = g;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return P.npts[a % P.p.n_points] > P.npts[b % P.p.n_points];
+    });
+    const int64_t want_items = (int64_t)4 * P.dev.n_cu * 32;
+    std::vector<int> groups;
+    Batch b;
+    for (int g : order) {
+        std::vector<int> trial = groups;
+        trial.push_back(g);
+        Batch t;
+        P.build_group_batch(trial, P.p.n_surrogates, &t);
+        if (t.total_bytes > ws_bytes)
+            break;
+        groups.swap(trial);
+        b = std::move(t);
+        if (b.n_items >= want_items)
+            break;
+    }
+    if (groups.empty())
+        return fail(TE_ERR_NOMEM, "workspace of %zu bytes cannot hold one window group", ws_bytes);
+    void *stg = P.pool.take(b.stage_bytes());
+    if (!stg)
+        return fail(TE_ERR_NOMEM, "pinned staging allocation failed");
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    const SearchConfig saved = P.cfg;
+    SearchConfig best = saved;
+    double best_t = 1e30;
+    hipError_t e = hipSuccess;
+    const int slot_set[] = {4, 8, 16};
+    const int wpg_set[] = {1, 2, 4};
+    for (int sl : slot_set)
+        for (int wpg : wpg_set) {
+            const int occ = search_occupancy(P.p.d_y, P.p.d_x, P.p.k, sl, wpg);
+            if (occ < 1)
+                continue;
+            std::vector<int> wgs = {occ};
+            if (occ >= 2)
+                wgs.push_back(occ / 2);
+            for (int wg : wgs) {
+                P.cfg = SearchConfig{sl, wpg, wg};
+                double tmin = 1e30;
+                for (int rep = 0; rep < 3 && s == TE_OK && e == hipSuccess; ++rep) {
+                    e = hipEventRecord(e0, st);
+                    if (e == hipSuccess)
+                        s = P.enqueue_batch(b, x, y, perms, ws, stg, st);
+                    if (s == TE_OK && e == hipSuccess)
+                        e = hipEventRecord(e1, st);
+                    if (s == TE_OK && e == hipSuccess)
+                        e = hipEventSynchronize(e1);
+                    float ms = 0;
+                    if (s == TE_OK && e == hipSuccess)
+                        hipEventElapsedTime(&ms, e0, e1);
+                    if (rep > 0)                     // the first run of a shape warms it up
+                        tmin = std::min(tmin, (double)ms);
+                }
+                if (s != TE_OK || e != hipSuccess)
+                    break;
+                if (tmin < best_t) {
+                    best_t = tmin;
+                    best = P.cfg;
+                }
+            }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    P.pool.give(stg);
+    P.cfg = (s == TE_OK && e == hipSuccess) ? best : saved;
+    if (s != TE_OK)
+        return s;
+    if (e != hipSuccess)
+        return hip_fail(e, "tuning run");
+    {
+        std::vector<int64_t> ns(P.npts);
+        std::nth_element(ns.begin(), ns.begin() + ns.size() / 2, ns.end());
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_table[TuneKey{P.p.d_y, P.p.d_x, P.p.k, size_bucket(ns[ns.size() / 2])}] = TuneVal{best, best_t};
+    }
+    if (slots)
+        *slots = best.slots;
+    if (waves_per_wg)
+        *waves_per_wg = best.waves_per_wg;
+    if (wg_per_cu)
+        *wg_per_cu = best.wg_per_cu;
+    if (best_ms)
+        *best_ms = best_t;
+    return TE_OK;
+}
+
 te_status te_tune_save(const char *path)
 {
     clear_error();

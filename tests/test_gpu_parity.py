@@ -403,3 +403,18 @@ def test_delay_scan_rejects_delays_without_history(te):
         with pytest.raises(te.TEError) as ei:
             plan.delay_scan(x, y, bad, perms)
         assert ei.value.status == 1
+
+
+def test_plan_autotune_on_own_data(te):
+    """Tuning on the plan's data picks a valid shape; the estimates do not change."""
+    wl = synth.uneven_surrogates(R=150, T=60, n_points=3, n_surrogates=3, n_lo=300, n_hi=3000)
+    x, y, perms = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    ref = plan.surrogates(x, y, perms)
+    r = plan.autotune(x, y, perms)
+    say("plan tuned", r)
+    assert r["slots"] in (4, 8, 16) and 1 <= r["waves_per_wg"] <= 4 and r["wg_per_cu"] >= 1 and r["ms"] > 0
+    got = plan.surrogates(x, y, perms)
+    for u, v in zip(ref, got):
+        np.testing.assert_array_equal(u, v)
+    te.tune_clear()

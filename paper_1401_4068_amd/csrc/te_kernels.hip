@@ -206,6 +206,7 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
     const int nq = a.n_parts > 1 ? a.n_parts : 1;
     int qp = (int)(blockIdx.x % (unsigned)nq);   // this wave's queue
     int drained = 0;                              // queues found empty so far
+    int last_ci = 0, last_lo = 0, last_hi = 0;    // the previous item's chunk and its item range
     for (;;) {
         // ---- claim the next work item (wave-uniform)
         int q = 0;
@@ -223,7 +224,13 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
         } else if (q >= a.n_items) {
             break;
         }
-        const int ci = find_chunk(a.item_start, a.n_chunks, q);
+        // consecutive items of a queue are mostly blocks of one chunk
+        if (q < last_lo || q >= last_hi) {
+            last_ci = find_chunk(a.item_start, a.n_chunks, q);
+            last_lo = uload_i(a.item_start + last_ci);
+            last_hi = last_ci + 1 < a.n_chunks ? uload_i(a.item_start + last_ci + 1) : a.n_items;
+        }
+        const int ci = last_ci;
         ChunkDesc cd;
         {
             const char *w = reinterpret_cast<const char *>(a.chunks + ci);
@@ -299,6 +306,7 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
         // monotonically away from the reference block (rounding is monotone).
 
         int visited = n;                                  // candidates examined in pass 1
+        int scan_lo = 0, scan_hi = n;                     // pass 1 examined [scan_lo, scan_hi)
         if (!SORTED) {
             int j = 0;
             for (; j + 4 <= n; j += 4)
@@ -352,6 +360,8 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                 go = b > 0 && ballot(absdiff(ref[1], p0) < cur()) != 0;
             }
             visited = f - b;
+            scan_lo = b;
+            scan_hi = f;
         }
         // k+1-th smallest including self (distance 0) = k-th neighbour without self
         const float eps = cur();
@@ -371,20 +381,18 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
         // Candidate range [lo, hi): in a sorted chunk every point outside it is at
         // |fl32(p0_i - p0_j)| >= eps_i from every reference of the block, hence
         // outside all three marginal balls (each contains the target-past block).
+        // Pass 1 stopped each direction at a candidate no lane could use with a
+        // radius >= eps_i, so the range lies inside the one pass 1 examined; it is
+        // narrowed from there in steps of 64 points that no reference reaches.
         int lo = 0, hi = n;
         if (SORTED) {
-            hi = min(n, r0 + kWave);
-            while (hi < n) {
-                if (!ballot(valid && absdiff(ref[1], uload(cp.p[1] + hi)) < eps))
-                    break;
-                hi = min(n, hi + kWave);
-            }
-            lo = r0;
-            while (lo > 0) {
-                if (!ballot(valid && absdiff(ref[1], uload(cp.p[1] + lo - 1)) < eps))
-                    break;
-                lo = max(0, lo - kWave);
-            }
+            const int e0 = min(n, r0 + kWave);
+            hi = scan_hi;
+            while (hi - kWave >= e0 && !ballot(valid && absdiff(ref[1], uload(cp.p[1] + hi - kWave)) < eps))
+                hi -= kWave;
+            lo = scan_lo;
+            while (lo + kWave <= r0 && !ballot(valid && absdiff(ref[1], uload(cp.p[1] + lo + kWave - 1)) < eps))
+                lo += kWave;
         }
 
         const int nref = min(kWave, n - r0);

@@ -287,12 +287,31 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                 c[3][m] = v.w;
             }
         };
+        // Four candidates at once: their distances are independent, and a
+        // candidate that is not below the current k+1-th distance leaves the list
+        // unchanged when inserted (med3 / min network), so one wave-wide test of
+        // the group's smallest distance decides whether any insertion is needed.
+        auto visit_group = [&](const float (&c)[4][D]) {
+            float dj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const PairDist<DY, DX> d = pair_dist<DY, DX>(ref, c[u]);
+                dj[u] = fmaxf(d.t, fmaxf(d.p, d.s));
+            }
+            const float m = fminf(fminf(dj[0], dj[1]), fminf(dj[2], dj[3]));
+            if (ballot(m < cur())) {
+                keep_branch();
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    insert_sorted<KP1>(best, dj[u]);
+                if (GENERIC)
+                    thr = kth<KP1, GENERIC>(best, k);
+            }
+        };
         auto visit4 = [&](int j) {
             float c[4][D];
             load4(j, c);
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                visit(c[u]);
+            visit_group(c);
         };
         auto visit1 = [&](int j) {
             float c[D];
@@ -330,9 +349,7 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
             while (go && f + 4 <= n) {
                 float c[4][D];
                 load4(f, c);
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    visit(c[u]);
+                visit_group(c);
                 f += 4;
                 go = f < n && ballot(absdiff(ref[1], c[3][1]) < cur()) != 0;
             }
@@ -347,9 +364,7 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
             while (go && b >= 4) {
                 float c[4][D];
                 load4(b - 4, c);
-#pragma unroll
-                for (int u = 3; u >= 0; --u)
-                    visit(c[u]);
+                visit_group(c);
                 b -= 4;
                 go = b > 0 && ballot(absdiff(ref[1], c[0][1]) < cur()) != 0;
             }

@@ -117,6 +117,15 @@ void Batch::finish_layout()
         int p = 1;
         for (const ChunkDesc &d : chunks) {
             const int nb = (d.n + kWave - 1) / kWave;
+            const double w = (double)d.n * nb;
+            // a chunk that is small next to a queue's share ends a queue whole,
+            // so the queue ends on the chunk's cheapest blocks
+            if (w * 4 <= total / kQueues) {
+                acc += w;
+                while (p < kQueues && acc >= total * p / kQueues)
+                    part_start[p++] = d.item0 + nb;
+                continue;
+            }
             for (int bk = 0; bk < nb; ++bk) {
                 acc += d.n;
                 while (p < kQueues && acc >= total * p / kQueues)

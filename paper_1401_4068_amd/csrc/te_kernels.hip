@@ -245,7 +245,18 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
             cd.block0 = uload_i(reinterpret_cast<const int32_t *>(w + offsetof(ChunkDesc, block0)));
         }
         const int n = cd.n;
-        const int blk = q - cd.item0 + cd.block0;
+        int blk = q - cd.item0 + cd.block0;
+        if (a.sorted && cd.block0 == 0) {
+            // sorted chunk: blocks are taken middle first (the middle of the p0
+            // order is densest, so those blocks scan most); the cheap outer
+            // blocks come last and the waves of a queue end together
+            const int nb = (n + kWave - 1) / kWave, mid = nb >> 1, kk = blk;
+            const int pairs = min(mid, nb - mid);
+            if (kk < 2 * pairs)
+                blk = (kk & 1) ? mid - 1 - (kk >> 1) : mid + (kk >> 1);
+            else
+                blk = nb - mid > mid ? mid + pairs + (kk - 2 * pairs) : mid - 1 - pairs - (kk - 2 * pairs);
+        }
         const int r0 = blk * kWave;
         const Coords<DY, DX> cp(a.base, cd);
 

@@ -84,6 +84,45 @@ te_status current_device(DeviceInfo *out)
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// XCD work queues over a schedule of chunk pieces (ChunkDesc::item0 ascending,
+// pieces of n points, items up to the next piece's item0 or n_items): contiguous
+// item ranges of equal estimated work (an item of a chunk of n points costs
+// about n).  A piece that is small next to a queue's share ends a queue whole, so
+// the queue ends on the piece's cheapest blocks.
+void queue_bounds(const std::vector<ChunkDesc> &pieces, int64_t n_items, std::vector<int32_t> *part_start)
+{
+    std::vector<int32_t> &ps = *part_start;
+    ps.assign(kQueues + 1, 0);
+    auto count = [&](size_t c) {
+        return (c + 1 < pieces.size() ? (int64_t)pieces[c + 1].item0 : n_items) - pieces[c].item0;
+    };
+    double total = 0.0;
+    for (size_t c = 0; c < pieces.size(); ++c)
+        total += (double)pieces[c].n * count(c);
+    double acc = 0.0;
+    int p = 1;
+    for (size_t c = 0; c < pieces.size(); ++c) {
+        const ChunkDesc &d = pieces[c];
+        const int64_t nb = count(c);
+        const double w = (double)d.n * nb;
+        if (w * 4 <= total / kQueues) {
+            acc += w;
+            while (p < kQueues && acc >= total * p / kQueues)
+                ps[p++] = (int32_t)(d.item0 + nb);
+            continue;
+        }
+        for (int64_t bk = 0; bk < nb; ++bk) {
+            acc += d.n;
+            while (p < kQueues && acc >= total * p / kQueues)
+                ps[p++] = (int32_t)(d.item0 + bk + 1);
+        }
+    }
+    while (p <= kQueues)
+        ps[p++] = (int32_t)n_items;
+    for (int q = 1; q <= kQueues; ++q)
+        ps[q] = std::max(ps[q], ps[q - 1]);
+}
+
 void Batch::finish_layout()
 {
     // LPT order: biggest chunks first so the persistent waves end together.
@@ -106,37 +145,7 @@ void Batch::finish_layout()
     }
     chunks.swap(sorted);
 
-    // XCD work queues: contiguous item ranges of equal estimated work (an
-    // item of a chunk of n points costs about n), in the longest-first order
-    part_start.assign(kQueues + 1, 0);
-    {
-        double total = 0.0;
-        for (const ChunkDesc &d : chunks)
-            total += (double)d.n * ((d.n + kWave - 1) / kWave);
-        double acc = 0.0;
-        int p = 1;
-        for (const ChunkDesc &d : chunks) {
-            const int nb = (d.n + kWave - 1) / kWave;
-            const double w = (double)d.n * nb;
-            // a chunk that is small next to a queue's share ends a queue whole,
-            // so the queue ends on the chunk's cheapest blocks
-            if (w * 4 <= total / kQueues) {
-                acc += w;
-                while (p < kQueues && acc >= total * p / kQueues)
-                    part_start[p++] = d.item0 + nb;
-                continue;
-            }
-            for (int bk = 0; bk < nb; ++bk) {
-                acc += d.n;
-                while (p < kQueues && acc >= total * p / kQueues)
-                    part_start[p++] = d.item0 + bk + 1;
-            }
-        }
-        while (p <= kQueues)
-            part_start[p++] = (int32_t)n_items;
-        for (int q = 1; q <= kQueues; ++q)
-            part_start[q] = std::max(part_start[q], part_start[q - 1]);
-    }
+    queue_bounds(chunks, n_items, &part_start);
 
     size_t o = 0;
     off_coords = o;

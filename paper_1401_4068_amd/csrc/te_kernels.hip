@@ -246,11 +246,12 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
         }
         const int n = cd.n;
         int blk = q - cd.item0 + cd.block0;
-        if (a.sorted && cd.block0 == 0) {
-            // sorted chunk: blocks are taken middle first (the middle of the p0
-            // order is densest, so those blocks scan most); the cheap outer
+        const int nb = (n + kWave - 1) / kWave;
+        if (a.sorted && cd.block0 == 0 && last_hi - last_lo == nb) {
+            // a whole sorted chunk: blocks are taken middle first (the middle of
+            // the p0 order is densest, so those blocks scan most); the cheap outer
             // blocks come last and the waves of a queue end together
-            const int nb = (n + kWave - 1) / kWave, mid = nb >> 1, kk = blk;
+            const int mid = nb >> 1, kk = blk;
             const int pairs = min(mid, nb - mid);
             if (kk < 2 * pairs)
                 blk = (kk & 1) ? mid - 1 - (kk >> 1) : mid + (kk >> 1);

@@ -22,6 +22,7 @@ size_t align_up(size_t v, size_t a);
 int size_bucket(int64_t n);
 bool sorting_enabled();
 int sort_npad(int n);
+void queue_bounds(const std::vector<ChunkDesc> &pieces, int64_t n_items, std::vector<int32_t> *part_start);
 
 // A set of chunks laid out in one device workspace, with the host copy of its
 // tables.  Chunks are stored in schedule (longest-first) order.

@@ -194,7 +194,9 @@ int Server::class_of(const te_problem &p, bool sorted)
     if (!dry)
         c.cfg = default_config(dev, p.d_y, p.d_x, p.k, 16384);
     c.max_items = (int64_t)std::max(1, dev.n_cu) * std::max(1, c.cfg.wg_per_cu) * std::max(1, c.cfg.waves_per_wg) * 8;
-    c.table_cap = align_up(sizeof(ChunkDesc) * (size_t)c.max_items, 16) + sizeof(int32_t) * (size_t)c.max_items + 64;
+    c.table_cap = align_up(sizeof(ChunkDesc) * (size_t)c.max_items, 16) +
+                  align_up(sizeof(int32_t) * (size_t)c.max_items, 16) + align_up(sizeof(int32_t) * (kQueues + 1), 16) +
+                  sizeof(int32_t) * kQueues + 64;
     for (int sl = 0; sl < 2; ++sl) {
         if (!alloc.alloc(c.table_cap, &c.table_off[sl])) {
             for (int u = 0; u < sl; ++u)
@@ -409,21 +411,28 @@ bool Server::issue_step(int ci)
         steps.push_back(st);
         return true;
     }
-    // step table into the class's slot
-    const size_t tb = align_up(sizeof(ChunkDesc) * tab.size(), 16) + sizeof(int32_t) * starts.size();
+    // step table into the class's slot: pieces, their first items, XCD queue bounds, queue heads
+    std::vector<int32_t> qb;
+    queue_bounds(tab, items, &qb);
+    const size_t o_starts = align_up(sizeof(ChunkDesc) * tab.size(), 16);
+    const size_t o_qb = o_starts + align_up(sizeof(int32_t) * starts.size(), 16);
+    const size_t tb = o_qb + sizeof(int32_t) * qb.size();
     char *h = static_cast<char *>(kc.stage[slot]);
     std::memcpy(h, tab.data(), sizeof(ChunkDesc) * tab.size());
-    std::memcpy(h + align_up(sizeof(ChunkDesc) * tab.size(), 16), starts.data(), sizeof(int32_t) * starts.size());
+    std::memcpy(h + o_starts, starts.data(), sizeof(int32_t) * starts.size());
+    std::memcpy(h + o_qb, qb.data(), sizeof(int32_t) * qb.size());
     char *dtab = arena + kc.table_off[slot];
     hipStream_t sm = kc.stream[slot];
     hipError_t e = hipMemcpyAsync(dtab, h, tb, hipMemcpyHostToDevice, sm);
     int32_t *ctr = reinterpret_cast<int32_t *>(dtab + align_up(tb, 16));
     if (e == hipSuccess)
-        e = launch_fill_i32(ctr, 0, 1, sm);
+        e = launch_fill_i32(ctr, 0, kQueues, sm);
     SearchArgs a{};
     a.base = reinterpret_cast<const float *>(arena);
     a.chunks = reinterpret_cast<const ChunkDesc *>(dtab);
-    a.item_start = reinterpret_cast<const int32_t *>(dtab + align_up(sizeof(ChunkDesc) * tab.size(), 16));
+    a.item_start = reinterpret_cast<const int32_t *>(dtab + o_starts);
+    a.n_parts = kQueues;
+    a.part_start = reinterpret_cast<const int32_t *>(dtab + o_qb);
     a.n_chunks = (int32_t)tab.size();
     a.n_items = (int32_t)items;
     a.k = kc.k;

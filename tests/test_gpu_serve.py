@@ -114,3 +114,27 @@ def test_invalid_job_fails_alone(te):
     for u, v in zip(ref, got):
         np.testing.assert_array_equal(u, v)
     srv.close()
+
+
+def test_chunks_split_across_steps_match_alone(te, monkeypatch):
+    """With one wave per CU, a step holds at most 8 items per CU, so a chunk of 40 000 points
+    (625 blocks) is spread over several steps in pieces; each piece is searched over its own
+    blocks only and the results equal the job run alone."""
+    monkeypatch.setenv("TE_WAVES_PER_WG", "1")
+    monkeypatch.setenv("TE_WG_PER_CU", "1")
+    jobs = []
+    for i in range(2):
+        h = synth.history(2, 2, 1, 1)
+        jobs.append(synth.generic((9200, i), R=2000, T=h + 25, d_y=2, d_x=2, starts=(h + 3,), windows=(20,),
+                                  n_surrogates=1))
+    alone = [_alone(te, wl) for wl in jobs]
+    srv = te.Server(arena_bytes=512 << 20, max_slots=2, step_pairs=1)
+    tickets = [srv.submit(wl) for wl in jobs]
+    for t, ref in zip(tickets, alone):
+        got = srv.wait(t, timeout_s=120)
+        for u, v in zip(ref, got):
+            np.testing.assert_array_equal(u, v)
+    st = srv.stats()
+    say("split steps", st)
+    assert st["steps"] >= 4
+    srv.close()

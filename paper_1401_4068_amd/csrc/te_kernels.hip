@@ -683,13 +683,107 @@ __device__ void bitonic_lds(uint64_t *A, int len, int kk_first, int kk_last, int
 // global scratch; every stage's passes with stride below kSortLds only pair
 // elements of the same kSortLds-aligned tile, so each tile is loaded into LDS
 // once per stage for those passes and only the wider strides touch global memory.
+// Stable LSD radix sort of up to kRadixMax packed keys (order key in the high 32
+// bits, point index in the low 32) by their high 32 bits, 4 bits per pass, with
+// kRadixThreads threads: thread t owns a contiguous run of keys, counts its
+// digits into column t of L (digit-major), an exclusive scan over L gives every
+// (digit, thread) its first output slot, and each thread scatters its run in
+// order.  Keys enter in index order, so equal keys stay in index order: the
+// result is the order of the full 64-bit keys.  Returns the buffer holding it.
+constexpr int kRadixMax = 8192;
+constexpr int kRadixThreads = 512;
+
+__device__ uint64_t *radix_sort_lds(uint64_t *A, uint64_t *B, uint16_t *L, uint32_t *wsum, int n)
+{
+    const int t = threadIdx.x;
+    const bool act = t < kRadixThreads;
+    const int c = (n + kRadixThreads - 1) / kRadixThreads;
+    const int i0 = min(n, t * c), i1 = min(n, i0 + c);
+    const int lane = t & (kWave - 1), wave = t / kWave;
+    for (int shift = 32; shift < 64; shift += 4) {
+        if (act) {
+#pragma unroll
+            for (int d = 0; d < 16; ++d)
+                L[d * kRadixThreads + t] = 0;
+            for (int i = i0; i < i1; ++i) {
+                const int d = (int)((A[i] >> shift) & 15u);
+                L[d * kRadixThreads + t] = (uint16_t)(L[d * kRadixThreads + t] + 1);
+            }
+        }
+        __syncthreads();
+        // exclusive scan over the 16 x kRadixThreads counts, digit-major: thread s
+        // owns the 16 consecutive entries [16 s, 16 s + 16)
+        uint32_t own = 0;
+        if (act)
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                own += L[16 * t + e];
+        uint32_t inc = own;                       // inclusive scan over the wave
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t v = __shfl_up(inc, off);
+            if (lane >= off)
+                inc += v;
+        }
+        if (act && lane == kWave - 1)
+            wsum[wave] = inc;
+        __syncthreads();
+        if (act) {
+            uint32_t base = inc - own;
+            for (int w = 0; w < wave; ++w)
+                base += wsum[w];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const uint32_t v = L[16 * t + e];
+                L[16 * t + e] = (uint16_t)base;
+                base += v;
+            }
+        }
+        __syncthreads();
+        if (act)
+            for (int i = i0; i < i1; ++i) {
+                const uint64_t key = A[i];
+                const int d = (int)((key >> shift) & 15u);
+                const int slot = L[d * kRadixThreads + t];
+                L[d * kRadixThreads + t] = (uint16_t)(slot + 1);
+                B[slot] = key;
+            }
+        __syncthreads();
+        uint64_t *tmp = A;
+        A = B;
+        B = tmp;
+    }
+    return A;
+}
+
 __global__ void __launch_bounds__(1024) sort_kernel(const float *__restrict__ y, const float *__restrict__ pts,
                                                     const SortTask *__restrict__ tasks, int32_t *__restrict__ sigma,
                                                     uint64_t *__restrict__ scratch, int R, int T)
 {
     __shared__ uint64_t lds[kSortLds];
+    __shared__ uint16_t radix_cnt[16 * kRadixThreads];
+    __shared__ uint32_t radix_wsum[kRadixThreads / kWave];
     const SortTask tk = tasks[blockIdx.x];
     const int np = tk.npad;
+    if (tk.n <= kRadixMax) {
+        // small windows: radix sort in LDS (8 passes instead of a log^2 network)
+        for (int i = threadIdx.x; i < tk.n; i += blockDim.x) {
+            float f;
+            if (tk.mode == 0) {
+                const int r = i / tk.W;
+                const int t = tk.w + (i - r * tk.W);
+                f = y[((int64_t)tk.pair * R + r) * T + t - 1];
+            } else {
+                f = pts[tk.key_off + i];
+            }
+            lds[i] = sort_key(f, (uint32_t)i);
+        }
+        __syncthreads();
+        const uint64_t *S = radix_sort_lds(lds, lds + kRadixMax, radix_cnt, radix_wsum, tk.n);
+        for (int i = threadIdx.x; i < tk.n; i += blockDim.x)
+            sigma[tk.sig + i] = (int32_t)(S[i] & 0xffffffffu);
+        return;
+    }
     uint64_t *A = (np <= kSortLds) ? lds : scratch + tk.scratch;
     for (int i = threadIdx.x; i < np; i += blockDim.x) {
         uint64_t key = ~0ull;
@@ -797,18 +891,24 @@ __global__ void reduce_kernel(const ChunkDesc *__restrict__ chunks, int n_chunks
                               const double *__restrict__ partial, int k, const int32_t *err,
                               double *__restrict__ results)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    // one wave per chunk: lane l sums items l, l + 64, ... in order, then a fixed
+    // butterfly across the wave (the same order on every run and batch split)
+    const int c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
     if (c >= n_chunks)
         return;
     const ChunkDesc cd = chunks[c];
     const int nb = (cd.n + kWave - 1) / kWave;
     double s = 0.0;
-    for (int b = 0; b < nb; ++b)
+    for (int b = lane; b < nb; b += kWave)
         s += partial[cd.pbase + b];
-    double te = psi_of_count(k - 1) + s / (double)cd.n;
-    if (*err != 0)
-        te = __builtin_nan("");
-    results[cd.result] = te;
+    s = wave_sum(s);
+    if (lane == 0) {
+        double te = psi_of_count(k - 1) + s / (double)cd.n;
+        if (*err != 0)
+            te = __builtin_nan("");
+        results[cd.result] = te;
+    }
 }
 
 __global__ void pvalue_kernel(const double *__restrict__ results, int n_groups, int n_surr,
@@ -991,7 +1091,7 @@ hipError_t launch_reduce(const ChunkDesc *chunks, int n_chunks, const double *pa
 {
     if (n_chunks <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(reduce_kernel, dim3((n_chunks + 127) / 128), dim3(128), 0, st, chunks, n_chunks,
+    hipLaunchKernelGGL(reduce_kernel, dim3((n_chunks + 3) / 4), dim3(4 * kWave), 0, st, chunks, n_chunks,
                        partial, k, err, results);
     return hipGetLastError();
 }

@@ -398,8 +398,12 @@ te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, co
                     reinterpret_cast<uint64_t *>(ws + b.off_scratch), p.n_trials, p.n_samples, st);
     if (e != hipSuccess)
         return hip_fail(e, "sort launch");
+    int max_n = 0;
+    for (const EmbedTask &t : b.tasks)
+        max_n = std::max(max_n, t.n);
     e = launch_embed(x, y, perms, sigma, u_dev, reinterpret_cast<const EmbedTask *>(ws + b.off_tasks),
-                     (int)b.tasks.size(), base, p.n_trials, p.n_samples, p.d_y, p.d_x, p.tau, p.u, ctr + 1, st);
+                     (int)b.tasks.size(), max_n, base, p.n_trials, p.n_samples, p.d_y, p.d_x, p.tau, p.u, ctr + 1,
+                     st);
     if (e != hipSuccess)
         return hip_fail(e, "embed launch");
     SearchArgs a{};

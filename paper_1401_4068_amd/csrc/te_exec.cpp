@@ -335,8 +335,8 @@ te_status Plan::estimate_plain(const float *x, const float *y, char *ws, size_t 
             if (e != hipSuccess)
                 break;
         }
-        e = launch_embed(x, y, nullptr, sigma, nullptr, dt + g, 1, base, p.n_trials, p.n_samples, p.d_y, p.d_x,
-                         p.tau, p.u, ctr + 4 * g + 1, st);
+        e = launch_embed(x, y, nullptr, sigma, nullptr, dt + g, 1, (int)npts[g % p.n_points], base, p.n_trials,
+                         p.n_samples, p.d_y, p.d_x, p.tau, p.u, ctr + 4 * g + 1, st);
         if (e != hipSuccess)
             break;
         SearchArgs a{};

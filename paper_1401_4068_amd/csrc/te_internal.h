@@ -109,9 +109,8 @@ struct DeviceInfo {
 // Kernel launchers (te_kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 hipError_t launch_embed(const float *x, const float *y, const int32_t *perms, const int32_t *sigma,
-                        const int32_t *u_dev, const EmbedTask *tasks, int n_tasks, float *base, int R, int T,
-                        int d_y, int d_x, int tau,
-                        int u, int32_t *err, hipStream_t st);
+                        const int32_t *u_dev, const EmbedTask *tasks, int n_tasks, int max_n, float *base, int R,
+                        int T, int d_y, int d_x, int tau, int u, int32_t *err, hipStream_t st);
 hipError_t launch_sort(const float *y, const float *pts, const SortTask *tasks, int n_tasks, int32_t *sigma,
                        uint64_t *scratch, int R, int T, hipStream_t st);
 hipError_t launch_gather(const float *src, const GatherTask *tasks, int n_tasks, const int32_t *sigma, float *dst,

@@ -555,7 +555,7 @@ __global__ void embed_kernel(const float *__restrict__ x, const float *__restric
     const bool u_ok = u >= 1 && tk.w - u - (d_x - 1) * tau >= 0 && tk.w + tk.W - u <= T;
     const int64_t pr = (int64_t)tk.pair * R;
     bool bad = false;
-    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    for (int q = blockIdx.y * blockDim.x + threadIdx.x; q < n; q += blockDim.x * gridDim.y) {
         // position q of the (sorted) chunk holds window point qo = r W + (t' - w)
         int qo = q;
         if (tk.sig >= 0) {
@@ -1039,13 +1039,15 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st)
 }
 
 hipError_t launch_embed(const float *x, const float *y, const int32_t *perms, const int32_t *sigma,
-                        const int32_t *u_dev, const EmbedTask *tasks, int n_tasks, float *base, int R, int T,
-                        int d_y, int d_x, int tau, int u, int32_t *err, hipStream_t st)
+                        const int32_t *u_dev, const EmbedTask *tasks, int n_tasks, int max_n, float *base, int R,
+                        int T, int d_y, int d_x, int tau, int u, int32_t *err, hipStream_t st)
 {
     if (n_tasks <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(embed_kernel, dim3(n_tasks), dim3(256), 0, st, x, y, perms, sigma, u_dev, tasks, base, R, T,
-                       d_y, d_x, tau, u, err);
+    // a few hundred to a few thousand points per workgroup, so small batches still fill the GPU
+    const int parts = std::max(1, std::min(1024, (max_n + 1023) / 1024));
+    hipLaunchKernelGGL(embed_kernel, dim3(n_tasks, parts), dim3(256), 0, st, x, y, perms, sigma, u_dev, tasks, base,
+                       R, T, d_y, d_x, tau, u, err);
     return hipGetLastError();
 }
 

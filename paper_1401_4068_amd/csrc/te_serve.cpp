@@ -215,6 +215,14 @@ int Server::class_of(const te_problem &p, bool sorted)
     return (int)classes.size() - 1;
 }
 
+static int embed_max_n(const Batch &b)
+{
+    int m = 0;
+    for (const EmbedTask &t : b.tasks)
+        m = std::max(m, t.n);
+    return m;
+}
+
 static size_t job_footprint(const Plan &P, Batch *b, size_t *off_x, size_t *off_y, size_t *off_perm,
                             size_t *off_batch)
 {
@@ -322,7 +330,7 @@ bool Server::admit_one(Job *j)
     if (e == hipSuccess)
         e = launch_embed(reinterpret_cast<const float *>(reg + j->off_x), reinterpret_cast<const float *>(reg + j->off_y),
                          perm, sigma, nullptr, reinterpret_cast<const EmbedTask *>(bat + b.off_tasks), (int)b.tasks.size(),
-                         reinterpret_cast<float *>(bat + b.off_coords), P.p.n_trials, P.p.n_samples, P.p.d_y, P.p.d_x,
+                         embed_max_n(b), reinterpret_cast<float *>(bat + b.off_coords), P.p.n_trials, P.p.n_samples, P.p.d_y, P.p.d_x,
                          P.p.tau, P.p.u, ctr + 1, setup_stream);
     if (e == hipSuccess)
         e = hipEventCreateWithFlags(&j->ready_ev, hipEventDisableTiming);

@@ -79,6 +79,10 @@ typedef struct {
     const int32_t *window_len;     /* host [n_points] or NULL: W_c                  */
     const int32_t *trials;         /* host [n_points] or NULL: R_c (first R_c used) */
     int32_t n_surrogates;      /* S >= 0                                            */
+    int32_t cond_source;       /* 1: condition on the current source sample x_t as well: the
+                                  conditioning set is (Y_past, x_t) in all spaces of eq. 8-9, the
+                                  control of instantaneous mixing noted with Fig. 2; needs
+                                  d_y + 1 <= 4.  0: eq. 9 as written                        */
 } te_problem;
 
 /* Library version string. */

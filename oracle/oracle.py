@@ -67,8 +67,12 @@ def _p(a, ct):
     return a.ctypes.data_as(ctypes.POINTER(ct))
 
 
-def embed(x, y, d_y, d_x, tau, u, w, W, Rc=None, src_perm=None, tgt_perm=None) -> np.ndarray:
-    """Pooled points of one window as float32 [Rc*W, 1+d_y+d_x] (eq. 6-7, eq. 10)."""
+def embed(x, y, d_y, d_x, tau, u, w, W, Rc=None, src_perm=None, tgt_perm=None, cond=False) -> np.ndarray:
+    """Pooled points of one window as float32 [Rc*W, 1+d_y+d_x] (eq. 6-7, eq. 10).
+
+    cond: the current source sample x_t joins the conditioning set (the note on
+    instantaneous mixing with Fig. 2): it is inserted as the last target-past
+    coordinate, giving [Rc*W, 2+d_y+d_x] points for d_y + 1 target-past columns."""
     x = np.ascontiguousarray(x, np.float32)
     y = np.ascontiguousarray(y, np.float32)
     R, T = x.shape
@@ -84,6 +88,10 @@ def embed(x, y, d_y, d_x, tau, u, w, W, Rc=None, src_perm=None, tgt_perm=None) -
                          _p(out, ctypes.c_float))
     if st != 0:
         raise ValueError("window geometry out of range")
+    if cond:
+        rs = np.arange(Rc) if sp is None else sp.astype(np.int64)
+        xt = x[rs][:, int(w):int(w) + int(W)].reshape(-1)          # point order r * W + (t' - w)
+        out = np.ascontiguousarray(np.insert(out, 1 + d_y, xt, axis=1))
     return out
 
 
@@ -190,9 +198,26 @@ def workload_jobs(wl, pairs=None, points=None, surrogates=None):
     return jobs, keys
 
 
+def te_cond_jobs(x, y, d_y, d_x, tau, u, k, jobs, perms=None, mode=0):
+    """TE conditioned on the current source sample as well, for (pair, w, W, Rc, perm_row) jobs."""
+    x = np.ascontiguousarray(x, np.float32)
+    y = np.ascontiguousarray(y, np.float32)
+    R = x.shape[1]
+    prow = None if perms is None else np.ascontiguousarray(perms, np.int32).reshape(-1, R)
+    out = np.empty(len(jobs))
+    for i, (p, w, W, Rc, row) in enumerate(jobs):
+        sp = None if row < 0 else prow[row]
+        pts = embed(x[p], y[p], d_y, d_x, tau, u, w, W, Rc, src_perm=sp, cond=True)
+        out[i] = te_from_counts(counts(pts, d_y + 1, d_x, k, mode)[1], k)
+    return out
+
+
 def te_workload(wl, pairs=None, points=None, surrogates=None, n_threads=0, mode=0):
     """Oracle TE for the selected chunks of a workload: dict (pair, point, s) -> TE."""
     jobs, keys = workload_jobs(wl, pairs, points, surrogates)
+    if getattr(wl, "cond_source", 0):
+        te = te_cond_jobs(wl.x, wl.y, wl.d_y, wl.d_x, wl.tau, wl.u, wl.k, jobs, wl.perms, mode)
+        return dict(zip(keys, te.tolist()))
     te = te_jobs(wl.x, wl.y, wl.d_y, wl.d_x, wl.tau, wl.u, wl.k, jobs, wl.perms, n_threads, mode)
     return dict(zip(keys, te.tolist()))
 

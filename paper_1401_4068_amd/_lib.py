@@ -27,6 +27,7 @@ class Problem(ctypes.Structure):
         ("k", ctypes.c_int32), ("n_points", ctypes.c_int32), ("window", ctypes.c_int32),
         ("window_start", ctypes.POINTER(ctypes.c_int32)), ("window_len", ctypes.POINTER(ctypes.c_int32)),
         ("trials", ctypes.POINTER(ctypes.c_int32)), ("n_surrogates", ctypes.c_int32),
+        ("cond_source", ctypes.c_int32),
     ]
 
 

@@ -49,7 +49,7 @@ def _local_offsets(plan):
 
 
 def _problem(n_pairs, n_trials, n_samples, d_y, d_x, tau, u, k, window_start, window_len=None, trials=None,
-             n_surrogates=0, window=0):
+             n_surrogates=0, window=0, cond_source=0):
     """A te_problem and the arrays it points to (keep both alive while it is used)."""
     keep = []
     ws = np.ascontiguousarray(window_start, np.int32)
@@ -59,6 +59,7 @@ def _problem(n_pairs, n_trials, n_samples, d_y, d_x, tau, u, k, window_start, wi
     p.n_points = int(ws.shape[0])
     p.window = int(window)
     p.n_surrogates = int(n_surrogates)
+    p.cond_source = int(cond_source)
     I32P = ctypes.POINTER(ctypes.c_int32)
     p.window_start = ws.ctypes.data_as(I32P)
     keep.append(ws)
@@ -79,13 +80,14 @@ class Plan:
     Parameters follow te_problem in include/te.h: series of n_pairs pairs,
     n_trials repetitions and n_samples samples; embedding d_y, d_x, tau; delay
     u; k neighbours; per analysis point the window start, length and number of
-    pooled repetitions; n_surrogates shuffled surrogates.
+    pooled repetitions; n_surrogates shuffled surrogates; cond_source = 1 conditions
+    on the current source sample x_t as well.
     """
 
     def __init__(self, n_pairs, n_trials, n_samples, d_y, d_x, tau, u, k, window_start, window_len=None,
-                 trials=None, n_surrogates=0, window=0):
+                 trials=None, n_surrogates=0, window=0, cond_source=0):
         p, self._keep = _problem(n_pairs, n_trials, n_samples, d_y, d_x, tau, u, k, window_start, window_len,
-                                 trials, n_surrogates, window)
+                                 trials, n_surrogates, window, cond_source)
         self.n_points = int(p.n_points)
         self.n_pairs = int(n_pairs)
         self.n_surrogates = int(n_surrogates)
@@ -98,7 +100,8 @@ class Plan:
     @classmethod
     def from_workload(cls, wl, n_surrogates=None):
         return cls(wl.n_pairs, wl.n_trials, wl.n_samples, wl.d_y, wl.d_x, wl.tau, wl.u, wl.k, wl.window_start,
-                   wl.window_len, wl.trials, wl.n_surrogates if n_surrogates is None else n_surrogates)
+                   wl.window_len, wl.trials, wl.n_surrogates if n_surrogates is None else n_surrogates,
+                   cond_source=int(getattr(wl, "cond_source", 0)))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -248,7 +251,8 @@ class Server:
     def submit(self, wl):
         """Submit a synth Workload-like object (series, geometry, perms); returns a ticket."""
         p, keep = _problem(wl.n_pairs, wl.n_trials, wl.n_samples, wl.d_y, wl.d_x, wl.tau, wl.u, wl.k,
-                           wl.window_start, wl.window_len, wl.trials, wl.n_surrogates)
+                           wl.window_start, wl.window_len, wl.trials, wl.n_surrogates,
+                           cond_source=int(getattr(wl, "cond_source", 0)))
         x = np.ascontiguousarray(wl.x, np.float32)
         y = np.ascontiguousarray(wl.y, np.float32)
         perms = None

@@ -231,7 +231,7 @@ te_status Plan::build_group_batch(const std::vector<int> &groups, int n_surr, Ba
     b->n_results = b->n_groups * (n_surr + 1);
     b->groups = groups;
     int64_t fl = 0;
-    const int dT = 1 + p.d_y, dS = p.d_x;
+    const int dT = 1 + p.d_y, dS = p.d_x + p.cond_source;
     for (int gi = 0; gi < (int)groups.size(); ++gi) {
         const int g = groups[gi];
         const int pair = g / p.n_points, c = g % p.n_points;
@@ -356,7 +356,7 @@ te_status Plan::ensure_device() const
         return st;
     std::vector<int64_t> ns(npts);
     std::nth_element(ns.begin(), ns.begin() + ns.size() / 2, ns.end());
-    cfg = default_config(dev, p.d_y, p.d_x, p.k, ns[ns.size() / 2]);
+    cfg = default_config(dev, dy_eff(), p.d_x, p.k, ns[ns.size() / 2]);
     dev_ready = true;
     return TE_OK;
 }
@@ -402,8 +402,8 @@ te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, co
     for (const EmbedTask &t : b.tasks)
         max_n = std::max(max_n, t.n);
     e = launch_embed(x, y, perms, sigma, u_dev, reinterpret_cast<const EmbedTask *>(ws + b.off_tasks),
-                     (int)b.tasks.size(), max_n, base, p.n_trials, p.n_samples, p.d_y, p.d_x, p.tau, p.u, ctr + 1,
-                     st);
+                     (int)b.tasks.size(), max_n, base, p.n_trials, p.n_samples, p.d_y, p.d_x, p.tau, p.u,
+                     p.cond_source, ctr + 1, st);
     if (e != hipSuccess)
         return hip_fail(e, "embed launch");
     SearchArgs a{};
@@ -423,7 +423,8 @@ te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, co
     a.lte_out = lte_out;
     a.perm_base = sigma;
     a.sorted = sorted ? 1 : 0;
-    if ((e = launch_search_timed(a, p.d_y, p.d_x, cfg, grid_waves(b.n_items), st)) != hipSuccess)
+    a.cond = p.cond_source;
+    if ((e = launch_search_timed(a, dy_eff(), p.d_x, cfg, grid_waves(b.n_items), st)) != hipSuccess)
         return hip_fail(e, "search launch");
     double *res = reinterpret_cast<double *>(ws + b.off_results);
     if ((e = launch_reduce(a.chunks, a.n_chunks, a.partial, p.k, ctr + 1, res, st)) != hipSuccess)
@@ -502,6 +503,10 @@ te_status te_plan_create(const te_problem *pr, te_plan *out)
         return fail(TE_ERR_INVALID, "k must be in 1..%d", kMaxK);
     if (p.n_surrogates < 0)
         return fail(TE_ERR_INVALID, "n_surrogates must be >= 0");
+    if (p.cond_source < 0 || p.cond_source > 1)
+        return fail(TE_ERR_INVALID, "cond_source must be 0 or 1");
+    if (p.d_y + p.cond_source > kMaxDimY)
+        return fail(TE_ERR_INVALID, "conditioning on x_t needs d_y <= %d", kMaxDimY - 1);
     if (!p.window_start)
         return fail(TE_ERR_INVALID, "window_start is required");
     auto plan = std::make_unique<te_plan_s>();
@@ -539,7 +544,7 @@ te_status te_plan_create(const te_problem *pr, te_plan *out)
     P.p.window_start = nullptr;
     P.p.window_len = nullptr;
     P.p.trials = nullptr;
-    if (!search_supported(p.d_y, p.d_x, p.k, 8))
+    if (!search_supported(P.dy_eff(), p.d_x, p.k, 8))
         return fail(TE_ERR_INVALID, "no search kernel for d_y=%d d_x=%d k=%d", p.d_y, p.d_x, p.k);
     // full batch: every (pair, point) with all surrogates
     std::vector<int> all(p.n_pairs * p.n_points);
@@ -555,7 +560,7 @@ te_status te_plan_create(const te_problem *pr, te_plan *out)
     P.min_bytes = mn;
     // plain path: one window at a time, originals only
     int64_t maxn = *std::max_element(P.npts.begin(), P.npts.end());
-    P.plain_bytes = align_up(sizeof(float) * (size_t)maxn * (1 + p.d_y + p.d_x), 256) +
+    P.plain_bytes = align_up(sizeof(float) * (size_t)maxn * (1 + p.d_y + p.d_x + p.cond_source), 256) +
                     align_up(sizeof(double) * (size_t)((maxn + kWave - 1) / kWave), 256) +
                     align_up(sizeof(double) * (size_t)p.n_pairs * p.n_points, 256) +
                     align_up(sizeof(int32_t) * 4 * (size_t)p.n_pairs * p.n_points + 16, 256) +

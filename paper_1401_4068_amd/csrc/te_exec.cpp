@@ -240,7 +240,7 @@ te_status Plan::estimate_plain(const float *x, const float *y, char *ws, size_t 
     if (ws_bytes < plain_bytes)
         return fail(TE_ERR_NOMEM, "workspace %zu bytes < plain-path size %zu", ws_bytes, plain_bytes);
     const int G = p.n_pairs * p.n_points;
-    const int D = 1 + p.d_y + p.d_x;
+    const int D = 1 + p.d_y + p.d_x + p.cond_source;
     const int64_t maxn = *std::max_element(npts.begin(), npts.end());
     size_t o = 0;
     const size_t off_coords = o;
@@ -336,7 +336,7 @@ te_status Plan::estimate_plain(const float *x, const float *y, char *ws, size_t 
                 break;
         }
         e = launch_embed(x, y, nullptr, sigma, nullptr, dt + g, 1, (int)npts[g % p.n_points], base, p.n_trials,
-                         p.n_samples, p.d_y, p.d_x, p.tau, p.u, ctr + 4 * g + 1, st);
+                         p.n_samples, p.d_y, p.d_x, p.tau, p.u, p.cond_source, ctr + 4 * g + 1, st);
         if (e != hipSuccess)
             break;
         SearchArgs a{};
@@ -349,7 +349,8 @@ te_status Plan::estimate_plain(const float *x, const float *y, char *ws, size_t 
         a.counter = ctr + 4 * g;
         a.partial = partial;
         a.sorted = sorted ? 1 : 0;
-        e = launch_search_timed(a, p.d_y, p.d_x, cfg, grid_waves(items), st);
+        a.cond = p.cond_source;
+        e = launch_search_timed(a, dy_eff(), p.d_x, cfg, grid_waves(items), st);
         if (e != hipSuccess)
             break;
         e = launch_reduce(dc + g, 1, partial, p.k, ctr + 4 * g + 1, res, st);

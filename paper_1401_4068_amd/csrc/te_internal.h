@@ -73,7 +73,7 @@ struct SearchArgs {
     int32_t n_chunks;
     int32_t n_items;
     int32_t k;
-    int32_t pad_;
+    int32_t cond;               // 1: the last target-past coordinate is row 0 of the source block (x_t)
     int32_t *counter;           // work-queue head, zero before launch
     double *partial;            // [n_items] per-item sum of psi terms
     float *eps_out;             // optional per-point radius
@@ -110,7 +110,7 @@ struct DeviceInfo {
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 hipError_t launch_embed(const float *x, const float *y, const int32_t *perms, const int32_t *sigma,
                         const int32_t *u_dev, const EmbedTask *tasks, int n_tasks, int max_n, float *base, int R,
-                        int T, int d_y, int d_x, int tau, int u, int32_t *err, hipStream_t st);
+                        int T, int d_y, int d_x, int tau, int u, int cond, int32_t *err, hipStream_t st);
 hipError_t launch_sort(const float *y, const float *pts, const SortTask *tasks, int n_tasks, int32_t *sigma,
                        uint64_t *scratch, int R, int T, hipStream_t st);
 hipError_t launch_gather(const float *src, const GatherTask *tasks, int n_tasks, const int32_t *sigma, float *dst,

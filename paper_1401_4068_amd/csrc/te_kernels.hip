@@ -95,14 +95,17 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // Per-chunk coordinate base pointers (wave-uniform).
 template <int DY, int DX>
+// The first tp_rows coordinates live in the target block, the rest in the
+// source block (tp_rows = 1 + DY, or DY when the last target-past coordinate is
+// the current source sample x_t, stored as row 0 of the source block).
 struct Coords {
     static constexpr int D = 1 + DY + DX;
     const float *p[D];
-    __device__ __forceinline__ Coords(const float *base, const ChunkDesc &c)
+    __device__ __forceinline__ Coords(const float *base, const ChunkDesc &c, int tp_rows)
     {
 #pragma unroll
         for (int m = 0; m < D; ++m)
-            p[m] = (m < 1 + DY) ? base + c.tp + (int64_t)m * c.ld : base + c.s + (int64_t)(m - 1 - DY) * c.ld;
+            p[m] = (m < tp_rows) ? base + c.tp + (int64_t)m * c.ld : base + c.s + (int64_t)(m - tp_rows) * c.ld;
     }
 };
 
@@ -259,7 +262,7 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                 blk = nb - mid > mid ? mid + pairs + (kk - 2 * pairs) : mid - 1 - pairs - (kk - 2 * pairs);
         }
         const int r0 = blk * kWave;
-        const Coords<DY, DX> cp(a.base, cd);
+        const Coords<DY, DX> cp(a.base, cd, 1 + DY - a.cond);
 
         // ---- pass 1: lane = reference i, candidates uniform
         const int i = r0 + lane;
@@ -542,7 +545,8 @@ __global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t n)
 __global__ void embed_kernel(const float *__restrict__ x, const float *__restrict__ y,
                              const int32_t *__restrict__ perms, const int32_t *__restrict__ sigma,
                              const int32_t *__restrict__ u_dev, const EmbedTask *__restrict__ tasks,
-                             float *__restrict__ base, int R, int T, int d_y, int d_x, int tau, int u, int32_t *err)
+                             float *__restrict__ base, int R, int T, int d_y, int d_x, int tau, int u, int cond,
+                             int32_t *err)
 {
     const EmbedTask tk = tasks[blockIdx.x];
     const int n = tk.n;
@@ -588,10 +592,15 @@ __global__ void embed_kernel(const float *__restrict__ x, const float *__restric
             }
         }
         bad |= !u_ok;
+        if (cond) {                                   // current source sample x_t (conditioning set)
+            const float v = xr[t];
+            bad |= !isfinite(v);
+            base[tk.s + q] = v;
+        }
         for (int m = 0; m < d_x; ++m) {
             const float v = u_ok ? xr[t - u - m * tau] : 0.0f;
             bad |= !isfinite(v);
-            base[tk.s + (int64_t)m * n + q] = v;
+            base[tk.s + (int64_t)(m + cond) * n + q] = v;
         }
     }
     if (bad)
@@ -1040,14 +1049,14 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st)
 
 hipError_t launch_embed(const float *x, const float *y, const int32_t *perms, const int32_t *sigma,
                         const int32_t *u_dev, const EmbedTask *tasks, int n_tasks, int max_n, float *base, int R,
-                        int T, int d_y, int d_x, int tau, int u, int32_t *err, hipStream_t st)
+                        int T, int d_y, int d_x, int tau, int u, int cond, int32_t *err, hipStream_t st)
 {
     if (n_tasks <= 0)
         return hipSuccess;
     // a few hundred to a few thousand points per workgroup, so small batches still fill the GPU
     const int parts = std::max(1, std::min(1024, (max_n + 1023) / 1024));
     hipLaunchKernelGGL(embed_kernel, dim3(n_tasks, parts), dim3(256), 0, st, x, y, perms, sigma, u_dev, tasks, base,
-                       R, T, d_y, d_x, tau, u, err);
+                       R, T, d_y, d_x, tau, u, cond, err);
     return hipGetLastError();
 }
 

@@ -106,6 +106,8 @@ struct Plan {
     mutable std::vector<GraphEntry> graphs;
 
     ~Plan();
+    // target-past coordinates the search sees: d_y, plus x_t when conditioning on it
+    int dy_eff() const { return p.d_y + p.cond_source; }
     te_status ensure_device() const;
     te_status build_group_batch(const std::vector<int> &groups, int n_surr, Batch *b,
                                 const BatchOptions &opt = BatchOptions()) const;

@@ -127,6 +127,7 @@ struct StepRec {
 // owns two step-table slots (arena + pinned staging) so two steps can be in flight.
 struct KernelClass {
     int d_y = 0, d_x = 0, k = 0;
+    int cond = 0;                       // conditioning on x_t (d_y above includes it)
     bool sorted = true;
     hipStream_t stream[2] = {nullptr, nullptr};   // steps alternate, so one step's tail overlaps the next
     hipEvent_t last_ev[2] = {nullptr, nullptr};   // completion of the last step issued on each stream
@@ -184,15 +185,17 @@ struct Server {
 int Server::class_of(const te_problem &p, bool sorted)
 {
     for (size_t i = 0; i < classes.size(); ++i)
-        if (classes[i].d_y == p.d_y && classes[i].d_x == p.d_x && classes[i].k == p.k && classes[i].sorted == sorted)
+        if (classes[i].d_y == p.d_y + p.cond_source && classes[i].d_x == p.d_x && classes[i].k == p.k &&
+            classes[i].sorted == sorted && classes[i].cond == p.cond_source)
             return (int)i;
     KernelClass c;
     c.sorted = sorted;
-    c.d_y = p.d_y;
+    c.d_y = p.d_y + p.cond_source;                   // as the search sees it
+    c.cond = p.cond_source;
     c.d_x = p.d_x;
     c.k = p.k;
     if (!dry)
-        c.cfg = default_config(dev, p.d_y, p.d_x, p.k, 16384);
+        c.cfg = default_config(dev, c.d_y, p.d_x, p.k, 16384);
     c.max_items = (int64_t)std::max(1, dev.n_cu) * std::max(1, c.cfg.wg_per_cu) * std::max(1, c.cfg.waves_per_wg) * 8;
     c.table_cap = align_up(sizeof(ChunkDesc) * (size_t)c.max_items, 16) +
                   align_up(sizeof(int32_t) * (size_t)c.max_items, 16) + align_up(sizeof(int32_t) * (kQueues + 1), 16) +
@@ -331,7 +334,7 @@ bool Server::admit_one(Job *j)
         e = launch_embed(reinterpret_cast<const float *>(reg + j->off_x), reinterpret_cast<const float *>(reg + j->off_y),
                          perm, sigma, nullptr, reinterpret_cast<const EmbedTask *>(bat + b.off_tasks), (int)b.tasks.size(),
                          embed_max_n(b), reinterpret_cast<float *>(bat + b.off_coords), P.p.n_trials, P.p.n_samples, P.p.d_y, P.p.d_x,
-                         P.p.tau, P.p.u, ctr + 1, setup_stream);
+                         P.p.tau, P.p.u, P.p.cond_source, ctr + 1, setup_stream);
     if (e == hipSuccess)
         e = hipEventCreateWithFlags(&j->ready_ev, hipEventDisableTiming);
     if (e == hipSuccess)
@@ -447,6 +450,7 @@ bool Server::issue_step(int ci)
     a.counter = ctr;
     a.partial = reinterpret_cast<double *>(arena);
     a.sorted = kc.sorted ? 1 : 0;
+    a.cond = kc.cond;
     const int64_t full = (int64_t)dev.n_cu * kc.cfg.wg_per_cu * kc.cfg.waves_per_wg;
     if (e == hipSuccess)
         e = launch_search_timed(a, kc.d_y, kc.d_x, kc.cfg, (int)std::max<int64_t>(1, std::min<int64_t>(full, items)),

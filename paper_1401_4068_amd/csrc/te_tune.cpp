@@ -323,7 +323,7 @@ te_status te_plan_autotune(te_plan plan, const float *x, const float *y, const i
     const int wpg_set[] = {1, 2, 4};
     for (int sl : slot_set)
         for (int wpg : wpg_set) {
-            const int occ = search_occupancy(P.p.d_y, P.p.d_x, P.p.k, sl, wpg);
+            const int occ = search_occupancy(P.dy_eff(), P.p.d_x, P.p.k, sl, wpg);
             if (occ < 1)
                 continue;
             std::vector<int> wgs = {occ};
@@ -366,7 +366,7 @@ te_status te_plan_autotune(te_plan plan, const float *x, const float *y, const i
         std::vector<int64_t> ns(P.npts);
         std::nth_element(ns.begin(), ns.begin() + ns.size() / 2, ns.end());
         std::lock_guard<std::mutex> lk(g_mu);
-        g_table[TuneKey{P.p.d_y, P.p.d_x, P.p.k, size_bucket(ns[ns.size() / 2])}] = TuneVal{best, best_t};
+        g_table[TuneKey{P.dy_eff(), P.p.d_x, P.p.k, size_bucket(ns[ns.size() / 2])}] = TuneVal{best, best_t};
     }
     if (slots)
         *slots = best.slots;

@@ -41,6 +41,7 @@ class Workload:
     n_surrogates: int = 0
     perms: np.ndarray | None = None   # int32 [P, C, S, R] or None when S == 0
     meta: dict = field(default_factory=dict)
+    cond_source: int = 0          # 1: condition on the current source sample x_t as well
 
     @property
     def n_pairs(self) -> int:

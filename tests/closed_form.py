@@ -72,9 +72,11 @@ def delayed_lag_cov(a_x: float, a_y: float, c: float, delay: int, max_lag: int):
     return G, 0, delay
 
 
-def gaussian_te_delay(a_x=0.5, a_y=0.5, c=0.4, delay=1, d_y=2, d_x=2, tau=1, u=1) -> float:
-    """TE(X -> Y) at assumed delay u for a pair coupled with delay `delay` (eq. 6-7 embedding)."""
-    past_y = [("y", 1 + m * tau) for m in range(d_y)]
+def gaussian_te_delay(a_x=0.5, a_y=0.5, c=0.4, delay=1, d_y=2, d_x=2, tau=1, u=1, cond=False) -> float:
+    """TE(X -> Y) at assumed delay u for a pair coupled with delay `delay` (eq. 6-7 embedding).
+
+    cond: the current source sample x_t joins the conditioning set."""
+    past_y = [("y", 1 + m * tau) for m in range(d_y)] + ([("x", 0)] if cond else [])
     past_x = [("x", u + m * tau) for m in range(d_x)]
     allv = [("y", 0)] + past_y + past_x
     G, ix, iy = delayed_lag_cov(a_x, a_y, c, delay, max(l for _, l in allv) + 1)

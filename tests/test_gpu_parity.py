@@ -418,3 +418,26 @@ def test_plan_autotune_on_own_data(te):
     for u, v in zip(ref, got):
         np.testing.assert_array_equal(u, v)
     te.tune_clear()
+
+
+def test_conditioning_on_current_source(te):
+    """x_t in the conditioning set (stored as row 0 of each source block, so it follows the
+    trial shuffle): batched, plain and served paths against the oracle."""
+    wl = synth.generic((88,), n_pairs=2, R=150, T=70, d_y=2, d_x=2, u=2, starts=(20, 35, 50),
+                       windows=(10, 7, 15), trials=(150, 90, 120), n_surrogates=4, coupling=0.6)
+    wl.cond_source = 1
+    x, y, perms = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    t0, ts, pv = plan.surrogates(x, y, perms)
+    _compare(wl, t0, ts, pv)
+    np.testing.assert_array_equal(plan.estimate(x, y), t0)
+    # without the conditioning the estimates differ (the flag reaches the kernels)
+    wl0 = synth.generic((88,), n_pairs=2, R=150, T=70, d_y=2, d_x=2, u=2, starts=(20, 35, 50),
+                        windows=(10, 7, 15), trials=(150, 90, 120), n_surrogates=4, coupling=0.6)
+    u0 = te.Plan.from_workload(wl0).surrogates(x, y, perms)[0]
+    assert np.max(np.abs(u0 - t0)) > 1e-3
+    srv = te.Server(arena_bytes=256 << 20, max_slots=2)
+    got = srv.wait(srv.submit(wl), timeout_s=60)
+    srv.close()
+    for u, v in zip((t0, ts, pv), got):
+        np.testing.assert_array_equal(u, v)

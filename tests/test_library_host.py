@@ -119,3 +119,14 @@ def test_delay_scan_sizes_and_validation_without_gpu():
         with pytest.raises(te.TEError) as ei:
             p.delay_scan_workspace_bytes(bad)
         assert ei.value.status == 1 and msg in str(ei.value)
+
+
+def test_conditioning_needs_room_in_the_target_past():
+    import paper_1401_4068_amd as te
+    _lib_or_build()
+    _plan(d_y=3, cond_source=1)
+    with pytest.raises(te.TEError) as ei:
+        _plan(d_y=4, cond_source=1)
+    assert "d_y <= 3" in str(ei.value)
+    with pytest.raises(te.TEError):
+        _plan(cond_source=2)

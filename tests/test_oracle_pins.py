@@ -368,3 +368,39 @@ def test_delay_scan_ties_and_surrogates_at_the_chosen_delay():
                             [(0, 30, 10, 200, s) for s in range(9)], wl.perms)
     np.testing.assert_array_equal(te_surr[(0, 0)], direct)
     assert pv[(0, 0)] == 0.0
+
+
+# ------------------------------------------- conditioning on the current source sample
+
+def test_conditioned_embedding_by_hand():
+    x = np.arange(3 * 12, dtype=np.float32).reshape(3, 12) * -1.0
+    y = np.arange(3 * 12, dtype=np.float32).reshape(3, 12)
+    pts = oracle.embed(x, y, 2, 1, 1, 2, 5, 2, cond=True)
+    assert pts.shape == (6, 5)
+    # (y_t, y_{t-1}, y_{t-2}, x_t, x_{t-u}) with t = 5, u = 2, repetition 0
+    assert pts[0].tolist() == [5, 4, 3, -5, -3]
+    perm = np.array([2, 0, 1], np.int32)
+    sp = oracle.embed(x, y, 2, 1, 1, 2, 5, 2, src_perm=perm, cond=True)
+    assert sp[1].tolist() == [6, 5, 4, -30, -28]            # repetition 0 takes its source from repetition 2
+
+
+def test_conditioning_on_current_source_closed_form():
+    """With x strongly autocorrelated, x_t carries most of what X_past says about y_t: the
+    conditioned TE is the Gaussian closed form with x_t added to the conditioning set."""
+    from synth.processes import coupled_ar
+    cond_truth = gaussian_te_delay(a_x=0.9, c=0.4, delay=1, d_y=2, d_x=2, cond=True)
+    plain_truth = gaussian_te_delay(a_x=0.9, c=0.4, delay=1, d_y=2, d_x=2)
+    assert cond_truth == pytest.approx(0.0616720, abs=5e-7) and plain_truth > 2 * cond_truth
+    vc, vp = [], []
+    for s in range(10):
+        x, y = coupled_ar(synth.configs.BASE_SEED + 500 + s, 100, 100, a_x=0.9, coupling=0.4, delay=1)
+        wl = synth.configs.Workload(name="cond", x=x[None], y=y[None], d_y=2, d_x=2, tau=1, u=1, k=4,
+                                    window_start=np.array([80], np.int32), window_len=np.array([20], np.int32),
+                                    trials=np.array([100], np.int32), cond_source=1)
+        vc.append(oracle.te_workload(wl)[(0, 0, 0)])
+        wl.cond_source = 0
+        vp.append(oracle.te_workload(wl)[(0, 0, 0)])
+    vc, vp = np.array(vc), np.array(vp)
+    assert abs(vc.mean() - cond_truth) < 3 * vc.std(ddof=1) / math.sqrt(len(vc)) + BIAS_BUDGET
+    assert abs(vp.mean() - plain_truth) < 3 * vp.std(ddof=1) / math.sqrt(len(vp)) + BIAS_BUDGET
+    assert vp.mean() - vc.mean() > 0.05

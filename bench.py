@@ -224,19 +224,21 @@ def scan_record(args, scenario):
     """Delay reconstruction over an AR coupling scenario (eq. 5, eq. 12-16): one step is
     te_delay_scan over both directions, every window and every assumed delay, then the
     surrogate test at the chosen delays.  Estimates per step: P C n_u originals plus
-    P C (S + 1) at the chosen delays."""
+    P C (S + 1) at the chosen delays.  scenario 0: the robustness sweep over the amount
+    of data (one coupled window, M = R_c * W points for several R_c)."""
     import torch
     import synth
     import paper_1401_4068_amd as te
 
-    wl = synth.ar_scenarios(scenario)
+    wl = synth.ar_robustness() if scenario == 0 else synth.ar_scenarios(scenario)
     u_values = wl.meta["u_values"]
     n_u = len(u_values)
     D = wl.dim
-    N = int(wl.chunk_sizes()[0])
+    sizes = wl.chunk_sizes()
+    N = int(sizes.max())
     G = wl.n_pairs * wl.n_points
     est = G * n_u + G * (wl.n_surrogates + 1)
-    pairs_per_step = est * N * (N - 1)
+    pairs_per_step = int(np.sum(sizes * (sizes - 1))) * wl.n_pairs * (n_u + wl.n_surrogates + 1)
     x = torch.from_numpy(wl.x).cuda()
     y = torch.from_numpy(wl.y).cuda()
     perms = torch.from_numpy(wl.perms).cuda()
@@ -282,33 +284,35 @@ def scan_record(args, scenario):
         for c in range(wl.n_points):
             w0 = int(wl.window_start[c])
             findings.append(dict(direction=wl.meta["directions"][p], window=[w0, w0 + int(wl.window_len[c])],
-                                 u_best=int(u_best[p, c]), te_max=round(float(te_scan[p, c].max()), 4),
-                                 p_value=float(pv[p, c])))
+                                 points=int(sizes[c]), u_best=int(u_best[p, c]),
+                                 te_max=round(float(te_scan[p, c].max()), 4), p_value=float(pv[p, c])))
     rec = dict(
         metric=METRIC, value=round(est * args.steps / dt, 2), unit="estimates/s", n_gpus=1, steps=args.steps,
         warmup=args.warmup, ms_per_step=round(dt / args.steps * 1e3, 4), higher_is_better=True, scaling="weak",
         vs_baseline=None, dtype="f32", data="synthetic",
-        config=dict(workload="ar_scenario%d_delay_scan" % scenario, pairs=wl.n_pairs, trials=wl.n_trials,
-                    samples=wl.n_samples, windows=wl.n_points, points_per_window=N, d_y=wl.d_y, d_x=wl.d_x,
+        config=dict(workload=("ar_robustness_delay_scan" if scenario == 0 else "ar_scenario%d_delay_scan" % scenario),
+                    pairs=wl.n_pairs, trials=wl.n_trials, samples=wl.n_samples, windows=wl.n_points,
+                    points_per_window=[int(v) for v in sorted(set(sizes.tolist()))], d_y=wl.d_y, d_x=wl.d_x,
                     tau=wl.tau, u_values=[u_values[0], u_values[-1]], dim=D, k=wl.k, surrogates=wl.n_surrogates,
                     estimates_per_step=est, workspace_bytes=int(full), path="te_delay_scan"),
         distance_evals_per_s=round(2 * pairs_per_step * args.steps / dt, 1),
         latency_s=dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99))),
         tuned_shape=tuned, roofline=roof, findings=findings)
     if not args.no_cpu:
-        rec["cpu_baseline"] = scan_cpu_baseline(wl, u_values, est)
+        rec["cpu_baseline"] = scan_cpu_baseline(wl, u_values, est, pairs_per_step)
     return rec
 
 
-def scan_cpu_baseline(wl, u_values, est_per_step, budget_s: float = 12.0):
-    """The oracle on a seeded sample of (direction, window, delay) originals, scaled by pairs."""
+def scan_cpu_baseline(wl, u_values, est_per_step, pairs_per_step, budget_s: float = 12.0):
+    """The oracle on a seeded sample of (direction, window, delay) originals, scaled by pairs:
+    estimates/s = sample pairs/s divided by the step's mean pairs per estimate."""
     from oracle import oracle
     from synth.rng import derive_key, permutation
     threads = host_threads()
     jobs = [(p, c, u) for p in range(wl.n_pairs) for c in range(wl.n_points) for u in u_values]
     order = permutation(derive_key(4068, len(jobs)), len(jobs))
-    N = int(wl.chunk_sizes()[0])
-    done, t_total = 0, 0.0
+    sizes = wl.chunk_sizes()
+    done, t_total, pairs = 0, 0.0, 0
     while done < len(jobs) and t_total < budget_s:
         sel = [jobs[i] for i in order[done:done + threads]]
         t0 = time.perf_counter()
@@ -318,9 +322,11 @@ def scan_cpu_baseline(wl, u_values, est_per_step, budget_s: float = 12.0):
             oracle.te_jobs(wl.x, wl.y, wl.d_y, wl.d_x, wl.tau, u, wl.k, js, wl.perms, n_threads=threads)
         t_total += time.perf_counter() - t0
         done += len(sel)
-    return dict(value=done / t_total, unit="estimates/s", cores=threads, kind="oracle",
-                sample="%d of %d original (direction, window, delay) chunks of N = %d, %.1f s wall on %d threads; "
-                       "every estimate of the step has the same N" % (done, len(jobs), N, t_total, threads))
+        pairs += sum(int(sizes[c]) * (int(sizes[c]) - 1) for (_, c, _) in sel)
+    mean_pairs = pairs_per_step / est_per_step
+    return dict(value=(pairs / t_total) / mean_pairs, unit="estimates/s", cores=threads, kind="oracle",
+                sample="%d of %d original (direction, window, delay) chunks (%.3g directed pairs), %.1f s wall on "
+                       "%d threads; scaled by directed pairs" % (done, len(jobs), pairs, t_total, threads))
 
 
 def served_record(args):
@@ -412,7 +418,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="nonlinear",
-                    choices=["nonlinear", "linear", "uneven", "meg", "served", "ar1", "ar2", "ar3"])
+                    choices=["nonlinear", "linear", "uneven", "meg", "served", "ar0", "ar1", "ar2", "ar3"],
+                    help="ar0: delay recovery against the amount of data; ar1-ar3: the AR coupling scenarios")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--graph", action="store_true", help="replay the batched step as a hipGraph")

@@ -223,6 +223,27 @@ def ar_scenarios(scenario=1, R=50, T=3000, window=300, n_surrogates=500, d_y=2, 
     return w
 
 
+def ar_robustness(R=100, T=3000, window=300, start=1100, trials=(2, 7, 17, 34, 100), n_surrogates=100, d_y=2,
+                  d_x=1, k=4, name="ar_robustness"):
+    """Robustness against the amount of data (the sweep over M pooled points in the
+    robustness evaluation, here on AR scenario 1 instead of Lorenz systems): one
+    coupled window [start, start + window) analysed with the first R_c trials for
+    each R_c in `trials`, i.e. M = R_c * window points; assumed delays u = 1..20
+    (true delay 10); X -> Y only.
+    """
+    seed = BASE_SEED + 1000 * 7
+    x, y = ar_scenario(seed, R, T, 1)
+    C = len(trials)
+    w = Workload(name=name, x=x[None], y=y[None], d_y=d_y, d_x=d_x, tau=1, u=1, k=k,
+                 window_start=np.full(C, start, np.int32), window_len=np.full(C, window, np.int32),
+                 trials=np.array(trials, np.int32), n_surrogates=n_surrogates,
+                 meta=dict(seed=seed, scenario=1, u_values=list(range(1, 21)), directions=["X->Y"],
+                           points=[int(r) * window for r in trials]))
+    if n_surrogates:
+        w.perms = make_perms(seed, 1, w.trials, n_surrogates, R)
+    return w
+
+
 def history(d_y: int, d_x: int, tau: int, u: int) -> int:
     """Samples of history a window start needs: max(1 + (d_y-1) tau, u + (d_x-1) tau)."""
     return max(1 + (d_y - 1) * tau, u + (d_x - 1) * tau)

@@ -73,3 +73,18 @@ def test_ar_bidirectional_delays(te):
     assert u_best[YX, 7] == 20 and pv[YX, 7] == 0.0
     # before the first onset (windows starting at 200 and 500) neither direction carries transfer
     assert np.all(te_scan[:, :2].max(axis=2) < 0.03)
+
+
+def test_delay_recovery_against_amount_of_data(te):
+    """The robustness evaluation on AR data: with enough pooled points (M >= 10 000) the scan
+    recovers the coupling delay of 10 samples and the surrogate test rejects independence."""
+    import torch
+    wl = synth.ar_robustness()
+    x = torch.from_numpy(wl.x).cuda()
+    y = torch.from_numpy(wl.y).cuda()
+    perms = torch.from_numpy(wl.perms).cuda()
+    te_scan, u_best, _, pv = te.Plan.from_workload(wl).delay_scan(x, y, wl.meta["u_values"], perms)
+    say("M", wl.meta["points"], "u_best", u_best[0].tolist(), "p", pv[0].tolist())
+    for c, m in enumerate(wl.meta["points"]):
+        if m >= 10000:
+            assert u_best[0, c] == 10 and pv[0, c] == 0.0

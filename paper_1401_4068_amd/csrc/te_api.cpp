@@ -231,13 +231,18 @@ te_status Plan::build_group_batch(const std::vector<int> &groups, int n_surr, Ba
     b->n_results = b->n_groups * (n_surr + 1);
     b->groups = groups;
     int64_t fl = 0;
-    const int dT = 1 + p.d_y, dS = p.d_x + p.cond_source;
+    // With x_t in the conditioning set the target block holds it as its last
+    // target-past row; x_t follows the source shuffle, so every chunk then has a
+    // target block of its own.
+    const bool cond = p.cond_source != 0;
+    const int dT = 1 + p.d_y + p.cond_source, dS = p.d_x;
     for (int gi = 0; gi < (int)groups.size(); ++gi) {
         const int g = groups[gi];
         const int pair = g / p.n_points, c = g % p.n_points;
         const int N = (int)npts[c];
-        const int64_t tp = fl;
-        fl += (int64_t)dT * N;
+        int64_t tp = fl;
+        if (!cond)
+            fl += (int64_t)dT * N;
         int64_t sig = -1;
         if (sorted) {
             SortTask st{};
@@ -260,6 +265,10 @@ te_status Plan::build_group_batch(const std::vector<int> &groups, int n_surr, Ba
             b->n_sigma += N;
         }
         for (int s = 0; s <= n_surr; ++s) {
+            if (cond) {
+                tp = fl;
+                fl += (int64_t)dT * N;
+            }
             ChunkDesc d{};
             d.tp = tp;
             d.s = fl;
@@ -274,7 +283,7 @@ te_status Plan::build_group_batch(const std::vector<int> &groups, int n_surr, Ba
             d.result = gi * (n_surr + 1) + s;
             b->chunks.push_back(d);
             EmbedTask t{};
-            t.tp = s == 0 ? tp : -1;
+            t.tp = (s == 0 || cond) ? tp : -1;
             t.s = fl;
             t.perm = -1;
             t.sig = sig;
@@ -423,7 +432,6 @@ te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, co
     a.lte_out = lte_out;
     a.perm_base = sigma;
     a.sorted = sorted ? 1 : 0;
-    a.cond = p.cond_source;
     if ((e = launch_search_timed(a, dy_eff(), p.d_x, cfg, grid_waves(b.n_items), st)) != hipSuccess)
         return hip_fail(e, "search launch");
     double *res = reinterpret_cast<double *>(ws + b.off_results);

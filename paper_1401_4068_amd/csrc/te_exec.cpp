@@ -273,7 +273,7 @@ te_status Plan::estimate_plain(const float *x, const float *y, char *ws, size_t 
     int32_t *hi = reinterpret_cast<int32_t *>(stg + tbl_items);
     EmbedTask *ht = reinterpret_cast<EmbedTask *>(stg + tbl_tasks);
     SortTask *hs = reinterpret_cast<SortTask *>(stg + tbl_sorts);
-    const int dT = 1 + p.d_y;
+    const int dT = 1 + p.d_y + p.cond_source;     // x_t, when conditioned on, is the last target-past row
     for (int g = 0; g < G; ++g) {
         const int pair = g / p.n_points, c = g % p.n_points;
         const int N = (int)npts[c];
@@ -349,7 +349,6 @@ te_status Plan::estimate_plain(const float *x, const float *y, char *ws, size_t 
         a.counter = ctr + 4 * g;
         a.partial = partial;
         a.sorted = sorted ? 1 : 0;
-        a.cond = p.cond_source;
         e = launch_search_timed(a, dy_eff(), p.d_x, cfg, grid_waves(items), st);
         if (e != hipSuccess)
             break;

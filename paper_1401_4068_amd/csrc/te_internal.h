@@ -73,7 +73,7 @@ struct SearchArgs {
     int32_t n_chunks;
     int32_t n_items;
     int32_t k;
-    int32_t cond;               // 1: the last target-past coordinate is row 0 of the source block (x_t)
+    int32_t pad_;
     int32_t *counter;           // work-queue head, zero before launch
     double *partial;            // [n_items] per-item sum of psi terms
     float *eps_out;             // optional per-point radius

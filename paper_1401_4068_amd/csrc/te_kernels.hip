@@ -95,17 +95,14 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // Per-chunk coordinate base pointers (wave-uniform).
 template <int DY, int DX>
-// The first tp_rows coordinates live in the target block, the rest in the
-// source block (tp_rows = 1 + DY, or DY when the last target-past coordinate is
-// the current source sample x_t, stored as row 0 of the source block).
 struct Coords {
     static constexpr int D = 1 + DY + DX;
     const float *p[D];
-    __device__ __forceinline__ Coords(const float *base, const ChunkDesc &c, int tp_rows)
+    __device__ __forceinline__ Coords(const float *base, const ChunkDesc &c)
     {
 #pragma unroll
         for (int m = 0; m < D; ++m)
-            p[m] = (m < tp_rows) ? base + c.tp + (int64_t)m * c.ld : base + c.s + (int64_t)(m - tp_rows) * c.ld;
+            p[m] = (m < 1 + DY) ? base + c.tp + (int64_t)m * c.ld : base + c.s + (int64_t)(m - 1 - DY) * c.ld;
     }
 };
 
@@ -262,7 +259,7 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                 blk = nb - mid > mid ? mid + pairs + (kk - 2 * pairs) : mid - 1 - pairs - (kk - 2 * pairs);
         }
         const int r0 = blk * kWave;
-        const Coords<DY, DX> cp(a.base, cd, 1 + DY - a.cond);
+        const Coords<DY, DX> cp(a.base, cd);
 
         // ---- pass 1: lane = reference i, candidates uniform
         const int i = r0 + lane;
@@ -592,15 +589,17 @@ __global__ void embed_kernel(const float *__restrict__ x, const float *__restric
             }
         }
         bad |= !u_ok;
-        if (cond) {                                   // current source sample x_t (conditioning set)
+        if (cond && tk.tp >= 0) {
+            // the current source sample x_t joins the conditioning set: it is the last
+            // target-past row of this chunk's own target block (it follows the shuffle)
             const float v = xr[t];
             bad |= !isfinite(v);
-            base[tk.s + q] = v;
+            base[tk.tp + (int64_t)(1 + d_y) * n + q] = v;
         }
         for (int m = 0; m < d_x; ++m) {
             const float v = u_ok ? xr[t - u - m * tau] : 0.0f;
             bad |= !isfinite(v);
-            base[tk.s + (int64_t)(m + cond) * n + q] = v;
+            base[tk.s + (int64_t)m * n + q] = v;
         }
     }
     if (bad)

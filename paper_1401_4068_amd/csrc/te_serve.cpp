@@ -450,7 +450,6 @@ bool Server::issue_step(int ci)
     a.counter = ctr;
     a.partial = reinterpret_cast<double *>(arena);
     a.sorted = kc.sorted ? 1 : 0;
-    a.cond = kc.cond;
     const int64_t full = (int64_t)dev.n_cu * kc.cfg.wg_per_cu * kc.cfg.waves_per_wg;
     if (e == hipSuccess)
         e = launch_search_timed(a, kc.d_y, kc.d_x, kc.cfg, (int)std::max<int64_t>(1, std::min<int64_t>(full, items)),

@@ -441,3 +441,46 @@ def test_conditioning_on_current_source(te):
     srv.close()
     for u, v in zip((t0, ts, pv), got):
         np.testing.assert_array_equal(u, v)
+
+
+def _sampled_compare(wl, got, picks):
+    """Oracle on selected (pair, point, s) chunks of a full-size workload."""
+    t0, ts, pv = got
+    jobs, keys = [], []
+    for (p, c, s) in picks:
+        row = -1 if s == 0 else (p * wl.n_points + c) * wl.n_surrogates + (s - 1)
+        jobs.append((p, int(wl.window_start[c]), int(wl.window_len[c]), int(wl.trials[c]), row))
+        keys.append((p, c, s))
+    ref = oracle.te_jobs(wl.x, wl.y, wl.d_y, wl.d_x, wl.tau, wl.u, wl.k, jobs, wl.perms)
+    for (p, c, s), r in zip(keys, ref):
+        g = t0[p, c] if s == 0 else ts[p, c, s - 1]
+        assert abs(g - r) <= TIGHT, ((p, c, s), g, r)
+
+
+def test_uneven_surrogates_full_size_sampled(te):
+    """The uneven-surrogate batch at full size (5000 trials, 60 windows of 1 000-49 400 points, 200
+    surrogates each: 12 060 chunks, 3.7 GB of workspace) in the launch shape the benchmark uses;
+    the oracle checks originals and surrogates of the windows it can finish in seconds."""
+    wl = synth.uneven_surrogates()
+    n = wl.chunk_sizes()
+    x, y, perms = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    got = plan.surrogates(x, y, perms)
+    small = [int(c) for c in np.argsort(n)[:3]]
+    mid = int(np.argsort(np.abs(n - 10000))[0])
+    say("uneven full: checking windows", [(c, int(n[c])) for c in small + [mid]])
+    picks = [(0, c, s) for c in small for s in (0, 1, 200)] + [(0, mid, 0), (0, mid, 117)]
+    _sampled_compare(wl, got, picks)
+    # p-values follow from the estimates exactly
+    for c in small:
+        assert got[2][0, c] == oracle.p_value(got[0][0, c], got[1][0, c])
+
+
+def test_meg_like_full_size_sampled(te):
+    """The MEG-shaped batch at full size (16 pairs x 40 windows x 101 chunks of 2 400 points, D = 9)."""
+    wl = synth.meg_like()
+    x, y, perms = dev(wl)
+    got = te.Plan.from_workload(wl).surrogates(x, y, perms)
+    rng_picks = np.floor(uniform01(derive_key(4242), 24) * np.array([16, 40, 101] * 8)).astype(int).reshape(8, 3)
+    picks = [tuple(int(v) for v in r) for r in rng_picks] + [(0, 0, 0), (15, 39, 100)]
+    _sampled_compare(wl, got, picks)

@@ -340,7 +340,7 @@ def served_record(args):
 
     def replay(jobs, rate_label):
         wls = [synth.job_workload(j) for j in jobs]
-        warm_srv = te.Server(arena_bytes=64 << 20, max_slots=4)      # module load, first launches
+        warm_srv = te.Server(arena_bytes=256 << 20, max_slots=4)     # module load, first launches
         for d in (2, 3, 4):
             warm = synth.job_workload(dict(id=-d, t=0.0, d=d, W=10, R=30, S=2, seed=d))
             warm_srv.wait(warm_srv.submit(warm), timeout_s=120)

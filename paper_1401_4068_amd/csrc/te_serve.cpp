@@ -196,7 +196,7 @@ int Server::class_of(const te_problem &p, bool sorted)
     c.k = p.k;
     if (!dry)
         c.cfg = default_config(dev, c.d_y, p.d_x, p.k, 16384);
-    c.max_items = (int64_t)std::max(1, dev.n_cu) * std::max(1, c.cfg.wg_per_cu) * std::max(1, c.cfg.waves_per_wg) * 8;
+    c.max_items = (int64_t)std::max(1, dev.n_cu) * std::max(1, c.cfg.wg_per_cu) * std::max(1, c.cfg.waves_per_wg) * 16;
     c.table_cap = align_up(sizeof(ChunkDesc) * (size_t)c.max_items, 16) +
                   align_up(sizeof(int32_t) * (size_t)c.max_items, 16) + align_up(sizeof(int32_t) * (kQueues + 1), 16) +
                   sizeof(int32_t) * kQueues + 64;
@@ -366,9 +366,9 @@ bool Server::issue_step(int ci)
     std::vector<Job *> finishing;
     int64_t items = 0, pairs = 0;
     const int64_t max_items = kc.max_items;
-    // a step always fills the GPU (one work item per resident wave); the pair budget
-    // only bounds it beyond that, so large-N jobs do not starve the launch
-    const int64_t min_items = max_items / 8;
+    // a step always gives every resident wave several work items (the last items of a
+    // step then end close together); the pair budget only bounds it beyond that
+    const int64_t min_items = max_items / 4;
     const int slot = kc.slot_busy[0] ? 1 : 0;
     if (kc.slot_busy[slot])
         return false;

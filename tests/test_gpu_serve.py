@@ -69,7 +69,7 @@ def test_alone_equals_mix(te):
     st = srv.stats()
     say("stats", st)
     assert st["completed"] == len(jobs) and st["failed"] == 0
-    assert st["steps"] > len(set((wl.d_y for wl in jobs)))   # work was spread over many steps
+    assert st["steps"] >= len(set((wl.d_y for wl in jobs)))  # at least one step per kernel class
     assert st["peak_slots"] <= 5
     srv.close()
     # two jobs against the oracle
@@ -117,9 +117,10 @@ def test_invalid_job_fails_alone(te):
 
 
 def test_chunks_split_across_steps_match_alone(te, monkeypatch):
-    """With one wave per CU, a step holds at most 8 items per CU, so a chunk of 40 000 points
-    (625 blocks) is spread over several steps in pieces; each piece is searched over its own
-    blocks only and the results equal the job run alone."""
+    """With one wave per CU a step holds 4 to 16 items per CU (1 024 to 4 096 items on 256 CUs),
+    so the four chunks of 40 000 points (625 blocks each, 2 500 items) are spread over at least
+    three steps in pieces; each piece is searched over its own blocks only and the results equal
+    the jobs run alone."""
     monkeypatch.setenv("TE_WAVES_PER_WG", "1")
     monkeypatch.setenv("TE_WG_PER_CU", "1")
     jobs = []
@@ -136,5 +137,5 @@ def test_chunks_split_across_steps_match_alone(te, monkeypatch):
             np.testing.assert_array_equal(u, v)
     st = srv.stats()
     say("split steps", st)
-    assert st["steps"] >= 4
+    assert st["steps"] >= 3
     srv.close()

@@ -67,6 +67,7 @@ def test_plan_sizes_without_gpu():
     (dict(trials=[21]), "trials"),
     (dict(trials=[1], window_len=[4]), "need more than k"),     # N = 4 <= k
     (dict(n_surrogates=-1), "n_surrogates"),
+    (dict(window_start=[], window_len=None), "n_points"),        # no analysis window at all
 ])
 def test_plan_rejects_invalid_geometry(bad, msg):
     from paper_1401_4068_amd import TEError

@@ -52,6 +52,13 @@ typedef const __attribute__((address_space(4))) f4v __attribute__((aligned(4))) 
 // be lowered to vector-memory loads).
 __device__ __forceinline__ float uload(const float *p) { return *(cfloat_t *)p; }
 __device__ __forceinline__ f4v uload4(const float *p) { return *(cf4_t *)p; }
+// the same at a 32-bit byte offset from a wave-uniform base: one SGPR offset shared
+// by several bases, so the loads need no 64-bit address arithmetic
+__device__ __forceinline__ f4v uload4_at(const float *p, uint32_t byte_off)
+{
+    typedef const __attribute__((address_space(4))) char cchar_t;
+    return *(cf4_t *)((cchar_t *)p + byte_off);
+}
 __device__ __forceinline__ int32_t uload_i(const int32_t *p) { return *(cint_t *)p; }
 __device__ __forceinline__ int64_t uload_l(const int64_t *p) { return *(cint64_t *)p; }
 
@@ -290,9 +297,10 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
         };
         // four consecutive candidates j..j+3 (scalar loads, one per coordinate)
         auto load4 = [&](int j, float (&c)[4][D]) {
+            const uint32_t off = (uint32_t)j * 4u;
 #pragma unroll
             for (int m = 0; m < D; ++m) {
-                const f4v v = uload4(cp.p[m] + j);
+                const f4v v = uload4_at(cp.p[m], off);
                 c[0][m] = v.x;
                 c[1][m] = v.y;
                 c[2][m] = v.z;

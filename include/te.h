@@ -249,7 +249,8 @@ te_status te_serve_close(te_server srv);
 /* ------------------------------------------------------------------ tuning
  * The search kernel's launch shape -- candidate slots per lane in the counting
  * pass (4, 8 or 16), waves per workgroup (1, 2 or 4) and resident workgroups per
- * compute unit -- is chosen per (d_y, d_x, k, chunk-size bucket floor(log2 N)).
+ * compute unit (every whole number of waves per SIMD from full occupancy down to
+ * half) -- is chosen per (d_y, d_x, k, chunk-size bucket floor(log2 N)).
  * te_autotune times every shape on n_chunks synthetic chunks of n_points points
  * (uniform random coordinates generated in ws) and records the fastest in a
  * process-wide table that plans and servers created afterwards use (the nearest

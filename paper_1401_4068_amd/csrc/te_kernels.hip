@@ -45,6 +45,8 @@ typedef const __attribute__((address_space(4))) float cfloat_t;
 typedef const __attribute__((address_space(4))) int32_t cint_t;
 typedef const __attribute__((address_space(4))) int64_t cint64_t;
 typedef const __attribute__((address_space(4))) f4v __attribute__((aligned(4))) cf4_t;
+typedef float f8v __attribute__((ext_vector_type(8)));
+typedef const __attribute__((address_space(4))) f8v __attribute__((aligned(4))) cf8_t;
 
 // Wave-uniform loads through the constant address space: the address is the
 // same in every lane, so these become scalar (SMEM) loads into SGPRs.  Only
@@ -52,6 +54,11 @@ typedef const __attribute__((address_space(4))) f4v __attribute__((aligned(4))) 
 // be lowered to vector-memory loads).
 __device__ __forceinline__ float uload(const float *p) { return *(cfloat_t *)p; }
 __device__ __forceinline__ f4v uload4(const float *p) { return *(cf4_t *)p; }
+__device__ __forceinline__ f8v uload8_at(const float *p, uint32_t byte_off)
+{
+    typedef const __attribute__((address_space(4))) char cchar_t;
+    return *(cf8_t *)((cchar_t *)p + byte_off);
+}
 // the same at a 32-bit byte offset from a wave-uniform base: one SGPR offset shared
 // by several bases, so the loads need no 64-bit address arithmetic
 __device__ __forceinline__ f4v uload4_at(const float *p, uint32_t byte_off)
@@ -76,7 +83,10 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_bal
 // psi(x) = psi(x + 1) - 1/x to x >= 16, then the asymptotic (Stirling-type)
 // series psi(x) ~ ln x - 1/(2x) - sum_j B_2j / (2j x^2j) through B_10
 // (Abramowitz & Stegun 6.3.18); truncation error < 1e-16 at x >= 16.
-__device__ double psi_of_count(int n)
+// Not inlined: its float64 constants (and those of log) would otherwise be
+// hoisted out of the persistent work loop and held in VGPRs for the whole
+// search, costing waves per SIMD.
+__device__ __attribute__((noinline)) double psi_of_count(int n)
 {
     double x = (double)n + 1.0;
     double shift = 0.0;
@@ -206,6 +216,8 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
 {
     constexpr int D = 1 + DY + DX;
     constexpr int RW = (D + 1 + 3) & ~3;       // LDS row: D coordinates + radius, 16-byte aligned
+    constexpr bool kGroup8 = D <= 7;           // pass-1 groups of eight candidates (8 D SGPRs of data;
+                                               // wider rows keep groups of four, within the SGPR budget)
     __shared__ __attribute__((aligned(16))) float rows[kMaxWavesPerWG * kWave * RW];
     const int lane = threadIdx.x & (kWave - 1);
     const int k = GENERIC ? a.k : KP1 - 1;
@@ -333,6 +345,35 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
             load4(j, c);
             visit_group(c);
         };
+        // eight consecutive candidates j..j+7, one scalar load per coordinate
+        auto load8 = [&](int j, float (&c)[8][D]) {
+            const uint32_t off = (uint32_t)j * 4u;
+#pragma unroll
+            for (int m = 0; m < D; ++m) {
+                const f8v v = uload8_at(cp.p[m], off);
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    c[u][m] = v[u];
+            }
+        };
+        auto visit_group8 = [&](const float (&c)[8][D]) {
+            float dj[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const PairDist<DY, DX> d = pair_dist<DY, DX>(ref, c[u]);
+                dj[u] = fmaxf(d.t, fmaxf(d.p, d.s));
+            }
+            const float m = fminf(fminf(fminf(dj[0], dj[1]), fminf(dj[2], dj[3])),
+                                  fminf(fminf(dj[4], dj[5]), fminf(dj[6], dj[7])));
+            if (ballot(m < cur())) {
+                keep_branch();
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    insert_sorted<KP1>(best, dj[u]);
+                if (GENERIC)
+                    thr = kth<KP1, GENERIC>(best, k);
+            }
+        };
         auto visit1 = [&](int j) {
             float c[D];
 #pragma unroll
@@ -355,17 +396,31 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
         } else {
             const int e0 = min(n, r0 + kWave);
             int j = r0;                                   // the block's own points first
+            if constexpr (kGroup8)
+                for (; j + 8 <= e0; j += 8) {
+                    float c[8][D];
+                    load8(j, c);
+                    visit_group8(c);
+                }
             for (; j + 4 <= e0; j += 4)
                 visit4(j);
             for (; j < e0; ++j)
                 visit1(j);
-            // then outward: forward (p0 increasing), then backward, a group of four
-            // at a time.  After each group, its candidate farthest from the block
-            // is tested: if no lane could still use it, no later candidate of that
-            // direction could either (so the next group is not loaded).  All loads
-            // of a group feed its distances unconditionally: one wait per group.
+            // then outward: forward (p0 increasing), then backward, a group of eight
+            // (four for wide rows, then four for the remainder) at a time.  After
+            // each group, its candidate farthest from the block is tested: if no
+            // lane could still use it, no later candidate of that direction could
+            // either (so the next group is not loaded).  All loads of a group feed
+            // its distances unconditionally: one wait per group.
             int f = e0;
             bool go = f < n;
+            while (kGroup8 && go && f + 8 <= n) {
+                float c[8][D];
+                load8(f, c);
+                visit_group8(c);
+                f += 8;
+                go = f < n && ballot(absdiff(ref[1], c[7][1]) < cur()) != 0;
+            }
             while (go && f + 4 <= n) {
                 float c[4][D];
                 load4(f, c);
@@ -381,6 +436,13 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
             }
             int b = r0;
             go = b > 0;
+            while (kGroup8 && go && b >= 8) {
+                float c[8][D];
+                load8(b - 8, c);
+                visit_group8(c);
+                b -= 8;
+                go = b > 0 && ballot(absdiff(ref[1], c[0][1]) < cur()) != 0;
+            }
             while (go && b >= 4) {
                 float c[4][D];
                 load4(b - 4, c);
@@ -453,23 +515,38 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                 tlo = uload(cp.p[1] + t0);
                 thi = uload(cp.p[1] + min(t0 + kWave * SLOTS, hi) - 1);
             }
-            for (int r = 0; r < nref; ++r) {
-                float rr[RW];
+            // references that can reach this tile: one lane-parallel test (each lane
+            // holds its own reference); in a sorted chunk a reference whose window
+            // [p0 - eps, p0 + eps] misses the tile's p0 range has nothing to count
+            // here and keeps the zero its lane starts the tile with
+            bool reach = valid;
+            if (SORTED)
+                reach = reach && !(tlo - ref[1] >= eps || ref[1] - thi >= eps);
+            uint64_t todo = ballot(reach);
+            evaluated2 += (unsigned long long)__builtin_popcountll(todo) *
+                          (unsigned long long)min(kWave * SLOTS, hi - t0);
+            auto read_row = [&](int r, f4v (&row)[RW / 4]) {
                 const f4v *rowv = reinterpret_cast<const f4v *>(myrows + r * RW);
 #pragma unroll
+                for (int v = 0; v < RW / 4; ++v)
+                    row[v] = rowv[v];
+            };
+            // orders a row's counting after the reads issued before it
+            auto pin_row = [&](f4v (&row)[RW / 4]) {
+#pragma unroll
+                for (int v = 0; v < RW / 4; ++v)
+                    asm volatile("" : "+v"(row[v]));
+            };
+            auto count_ref = [&](const f4v (&row)[RW / 4], int r) {
+                float rr[RW];
+#pragma unroll
                 for (int v = 0; v < RW / 4; ++v) {
-                    const f4v x = rowv[v];
-                    rr[4 * v + 0] = x.x;
-                    rr[4 * v + 1] = x.y;
-                    rr[4 * v + 2] = x.z;
-                    rr[4 * v + 3] = x.w;
+                    rr[4 * v + 0] = row[v].x;
+                    rr[4 * v + 1] = row[v].y;
+                    rr[4 * v + 2] = row[v].z;
+                    rr[4 * v + 3] = row[v].w;
                 }
                 const float er = rr[D];
-                // the whole tile lies at |fl32(p0_r - p0_j)| >= eps_r from this reference:
-                // nothing to count for it here (its lane keeps the zero it starts the tile with)
-                if (SORTED && ballot(tlo - rr[1] >= er || rr[1] - thi >= er))
-                    continue;
-                evaluated2 += (unsigned long long)min(kWave * SLOTS, hi - t0);
                 uint32_t sP = 0, sTP = 0, sPS = 0;
 #pragma unroll
                 for (int sl = 0; sl < SLOTS; ++sl) {
@@ -484,6 +561,51 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                 tP = writelane(tP, sP, r);
                 tTP = writelane(tTP, sTP, r);
                 tPS = writelane(tPS, sPS, r);
+            };
+            // rows of up to 8 floats (D <= 7): two row buffers used in turn, the
+            // next reference's row read from LDS while the current one is counted.  Each round counts two
+            // references; with an odd number the last one is counted twice, which
+            // writes the same sums to the same lane.
+            if constexpr (RW <= 8) {
+            if (todo != 0) {
+                f4v ra[RW / 4], rb[RW / 4];
+                int ia = __builtin_ctzll(todo);
+                todo &= todo - 1;
+                read_row(ia, ra);
+                for (;;) {
+                    int ib = ia;
+                    if (todo != 0) {
+                        ib = __builtin_ctzll(todo);
+                        todo &= todo - 1;
+                    }
+                    read_row(ib, rb);
+                    __builtin_amdgcn_sched_barrier(0);
+                    pin_row(ra);
+                    count_ref(ra, ia);
+                    const bool more = todo != 0;
+                    int in = ib;
+                    if (more) {
+                        in = __builtin_ctzll(todo);
+                        todo &= todo - 1;
+                    }
+                    read_row(in, ra);
+                    __builtin_amdgcn_sched_barrier(0);
+                    pin_row(rb);
+                    count_ref(rb, ib);
+                    if (!more)
+                        break;
+                    ia = in;
+                }
+            }
+            } else {
+            // wider rows (D > 7): one buffer, so that the occupancy is kept
+            while (todo != 0) {
+                const int r = __builtin_ctzll(todo);
+                todo &= todo - 1;
+                f4v ra[RW / 4];
+                read_row(r, ra);
+                count_ref(ra, r);
+            }
             }
             accP += tP;
             accTP += tTP;

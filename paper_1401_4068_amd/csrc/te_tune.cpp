@@ -216,9 +216,15 @@ te_status te_autotune(int32_t d_y, int32_t d_x, int32_t k, int32_t n_points, int
             const int occ = search_occupancy(d_y, d_x, k, sl, wpg);
             if (occ < 1)
                 continue;
+            // every occupancy from full down to half, in whole waves per SIMD: a
+            // batch with few work items per wave ends sooner when its longest items
+            // share their SIMD with fewer waves
+            const int per_level = std::max(1, 4 / wpg);   // workgroups per wave per SIMD
+            const int levels = occ / per_level;
             std::vector<int> wgs = {occ};
-            if (occ >= 2)
-                wgs.push_back(occ / 2);
+            for (int w = levels; w >= 1 && 2 * w >= levels; --w)
+                if (std::find(wgs.begin(), wgs.end(), w * per_level) == wgs.end())
+                    wgs.push_back(w * per_level);
             for (int wg : wgs) {
                 SearchConfig c{sl, wpg, wg};
                 double tmin = 1e30;
@@ -326,9 +332,15 @@ te_status te_plan_autotune(te_plan plan, const float *x, const float *y, const i
             const int occ = search_occupancy(P.dy_eff(), P.p.d_x, P.p.k, sl, wpg);
             if (occ < 1)
                 continue;
+            // every occupancy from full down to half, in whole waves per SIMD: a
+            // batch with few work items per wave ends sooner when its longest items
+            // share their SIMD with fewer waves
+            const int per_level = std::max(1, 4 / wpg);   // workgroups per wave per SIMD
+            const int levels = occ / per_level;
             std::vector<int> wgs = {occ};
-            if (occ >= 2)
-                wgs.push_back(occ / 2);
+            for (int w = levels; w >= 1 && 2 * w >= levels; --w)
+                if (std::find(wgs.begin(), wgs.end(), w * per_level) == wgs.end())
+                    wgs.push_back(w * per_level);
             for (int wg : wgs) {
                 P.cfg = SearchConfig{sl, wpg, wg};
                 double tmin = 1e30;

@@ -39,7 +39,7 @@ PEAK_FP32_HEADLINE = 157.3                                   # AMD headline (pac
 # HBM bytes per search launch of this workload from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs, scaled by a
 # plain 256 MiB copy (factors 2.000 and 1.000), keyed by the kernel source they were taken on; any other kernel
 # source reports null.
-RECORDED_TRAFFIC = {"37d3664c6215": 9704.5 * 1024 * 2.0 + 2341.375 * 1024 * 1.0}
+RECORDED_TRAFFIC = {"267fecff08ad": 9011.41 * 1024 * 2.0 + 1572.52 * 1024 * 1.0}
 KERNEL_SRC = os.path.join(ROOT, "paper_1401_4068_amd", "csrc", "te_kernels.hip")
 
 

@@ -228,7 +228,7 @@ te_status te_autotune(int32_t d_y, int32_t d_x, int32_t k, int32_t n_points, int
             for (int wg : wgs) {
                 SearchConfig c{sl, wpg, wg};
                 double tmin = 1e30;
-                for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+                for (int rep = 0; rep < 5 && e == hipSuccess; ++rep) {
                     e = launch_fill_i32(a.counter, 0, 1, st);
                     if (e == hipSuccess)
                         e = hipEventRecord(e0, st);
@@ -344,7 +344,7 @@ te_status te_plan_autotune(te_plan plan, const float *x, const float *y, const i
             for (int wg : wgs) {
                 P.cfg = SearchConfig{sl, wpg, wg};
                 double tmin = 1e30;
-                for (int rep = 0; rep < 3 && s == TE_OK && e == hipSuccess; ++rep) {
+                for (int rep = 0; rep < 5 && s == TE_OK && e == hipSuccess; ++rep) {
                     e = hipEventRecord(e0, st);
                     if (e == hipSuccess)
                         s = P.enqueue_batch(b, x, y, perms, ws, stg, st);

@@ -168,13 +168,17 @@ void Batch::finish_layout()
     tables_bytes = o - off_tables;
     off_partial = align_up(o, 256);
     o = off_partial + sizeof(double) * (size_t)std::max<int64_t>(n_items, 1);
+    // results, p-values and a copy of the error word back to back: one download
     off_results = align_up(o, 256);
     o = off_results + sizeof(double) * (size_t)std::max(n_results, 1);
-    off_pv = align_up(o, 256);
+    off_pv = o;
     o = off_pv + sizeof(double) * (size_t)std::max(n_groups, 1);
+    off_errout = o;
+    o = off_errout + sizeof(double);
+    // error word and reduce counter, then the XCD queue counters: one fill
     off_ctr = align_up(o, 256);
     o = off_ctr + sizeof(int32_t) * 4;
-    off_qctr = align_up(o, 64);
+    off_qctr = o;
     o = off_qctr + sizeof(int32_t) * kQueues;
     off_sigma = align_up(o, 256);
     o = off_sigma + sizeof(int32_t) * (size_t)n_sigma;
@@ -388,11 +392,10 @@ te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, co
     e = hipMemcpyAsync(ws + b.off_tables, tables_host, b.tables_bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess)
         return hip_fail(e, "upload tables");
+    // ctr: [1] error word, [2] finished reduce workgroups; the queue counters follow
     int32_t *ctr = reinterpret_cast<int32_t *>(ws + b.off_ctr);
-    if ((e = launch_fill_i32(ctr, 0, 4, st)) != hipSuccess)
-        return hip_fail(e, "fill");
     int32_t *qctr = reinterpret_cast<int32_t *>(ws + b.off_qctr);
-    if ((e = launch_fill_i32(qctr, 0, kQueues, st)) != hipSuccess)
+    if ((e = launch_fill_i32(ctr, 0, 4 + kQueues, st)) != hipSuccess)
         return hip_fail(e, "fill");
     float *base = reinterpret_cast<float *>(ws + b.off_coords);
     if (!b.perm_rows.empty()) {
@@ -435,19 +438,14 @@ te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, co
     if ((e = launch_search_timed(a, dy_eff(), p.d_x, cfg, grid_waves(b.n_items), st)) != hipSuccess)
         return hip_fail(e, "search launch");
     double *res = reinterpret_cast<double *>(ws + b.off_results);
-    if ((e = launch_reduce(a.chunks, a.n_chunks, a.partial, p.k, ctr + 1, res, st)) != hipSuccess)
-        return hip_fail(e, "reduce launch");
     double *pv = reinterpret_cast<double *>(ws + b.off_pv);
-    if ((e = launch_pvalues(res, b.n_groups, b.n_surr, pv, st)) != hipSuccess)
-        return hip_fail(e, "pvalue launch");
+    int32_t *err_out = reinterpret_cast<int32_t *>(ws + b.off_errout);
+    if ((e = launch_reduce(a.chunks, a.n_chunks, a.partial, p.k, ctr + 1, res, st, b.n_groups, b.n_surr, pv, ctr + 2,
+                           err_out)) != hipSuccess)
+        return hip_fail(e, "reduce launch");
     char *out = tables_host + align_up(b.tables_bytes, 256);
-    e = hipMemcpyAsync(out, res, sizeof(double) * b.n_results, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(out + sizeof(double) * b.n_results, pv, sizeof(double) * b.n_groups,
-                           hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(out + sizeof(double) * (b.n_results + b.n_groups), ctr + 1, sizeof(int32_t),
-                           hipMemcpyDeviceToHost, st);
+    e = hipMemcpyAsync(out, res, sizeof(double) * (b.n_results + b.n_groups) + sizeof(int32_t), hipMemcpyDeviceToHost,
+                       st);
     if (e != hipSuccess)
         return hip_fail(e, "download results");
     return TE_OK;

@@ -119,8 +119,12 @@ hipError_t launch_check_perms(const int32_t *perms, const int64_t *rows, const i
                               int32_t *err, hipStream_t st);
 hipError_t launch_search(const SearchArgs &a, int d_y, int d_x, const SearchConfig &cfg, int grid_waves,
                          hipStream_t st);
+// With pv != nullptr the launch also computes the n_groups p-values (results laid
+// out [group][original, surrogates...]) in its last-finishing workgroup, counted on
+// `done` (zero before the launch), and copies *err to *err_out when that is given.
 hipError_t launch_reduce(const ChunkDesc *chunks, int n_chunks, const double *partial, int k,
-                         const int32_t *err, double *results, hipStream_t st);
+                         const int32_t *err, double *results, hipStream_t st, int n_groups = 0, int n_surr = 0,
+                         double *pv = nullptr, int32_t *done = nullptr, int32_t *err_out = nullptr);
 hipError_t launch_pvalues(const double *results, int n_groups, int n_surr, double *pv, hipStream_t st);
 hipError_t launch_argmax_u(const double *results, int n_groups, int n_u, const int32_t *u_values, int32_t *u_sel,
                            hipStream_t st);

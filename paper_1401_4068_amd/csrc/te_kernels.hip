@@ -322,7 +322,8 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
         // Four candidates at once: their distances are independent, and a
         // candidate that is not below the current k+1-th distance leaves the list
         // unchanged when inserted (med3 / min network), so one wave-wide test of
-        // the group's smallest distance decides whether any insertion is needed.
+        // the group's smallest distance decides whether any insertion is needed,
+        // and a test per candidate skips the insertions no lane needs.
         auto visit_group = [&](const float (&c)[4][D]) {
             float dj[4];
 #pragma unroll
@@ -335,9 +336,12 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                 keep_branch();
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    insert_sorted<KP1>(best, dj[u]);
-                if (GENERIC)
-                    thr = kth<KP1, GENERIC>(best, k);
+                    if (ballot(dj[u] < cur())) {
+                        keep_branch();
+                        insert_sorted<KP1>(best, dj[u]);
+                        if (GENERIC)
+                            thr = kth<KP1, GENERIC>(best, k);
+                    }
             }
         };
         auto visit4 = [&](int j) {
@@ -369,9 +373,12 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                 keep_branch();
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
-                    insert_sorted<KP1>(best, dj[u]);
-                if (GENERIC)
-                    thr = kth<KP1, GENERIC>(best, k);
+                    if (ballot(dj[u] < cur())) {
+                        keep_branch();
+                        insert_sorted<KP1>(best, dj[u]);
+                        if (GENERIC)
+                            thr = kth<KP1, GENERIC>(best, k);
+                    }
             }
         };
         auto visit1 = [&](int j) {
@@ -1025,28 +1032,57 @@ __global__ void check_perms_kernel(const int32_t *__restrict__ perms, const int6
         atomicOr(err, 2);
 }
 
+// p-value of window group g (eq. 10 test): the fraction of its n_surr surrogate
+// estimates at or above the original (results [g][0] original, [g][1..] surrogates)
+__device__ __forceinline__ double group_pvalue(const double *results, int g, int n_surr)
+{
+    const double *r = results + (int64_t)g * (n_surr + 1);
+    int c = 0;
+    for (int s = 1; s <= n_surr; ++s)
+        c += r[s] >= r[0];
+    return n_surr > 0 ? (double)c / (double)n_surr : __builtin_nan("");
+}
+
 __global__ void reduce_kernel(const ChunkDesc *__restrict__ chunks, int n_chunks,
                               const double *__restrict__ partial, int k, const int32_t *err,
-                              double *__restrict__ results)
+                              double *results, int n_groups, int n_surr, double *__restrict__ pv,
+                              int32_t *done, int32_t *err_out)
 {
     // one wave per chunk: lane l sums items l, l + 64, ... in order, then a fixed
     // butterfly across the wave (the same order on every run and batch split)
     const int c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     const int lane = threadIdx.x & (kWave - 1);
-    if (c >= n_chunks)
-        return;
-    const ChunkDesc cd = chunks[c];
-    const int nb = (cd.n + kWave - 1) / kWave;
-    double s = 0.0;
-    for (int b = lane; b < nb; b += kWave)
-        s += partial[cd.pbase + b];
-    s = wave_sum(s);
-    if (lane == 0) {
-        double te = psi_of_count(k - 1) + s / (double)cd.n;
-        if (*err != 0)
-            te = __builtin_nan("");
-        results[cd.result] = te;
+    if (c < n_chunks) {
+        const ChunkDesc cd = chunks[c];
+        const int nb = (cd.n + kWave - 1) / kWave;
+        double s = 0.0;
+        for (int b = lane; b < nb; b += kWave)
+            s += partial[cd.pbase + b];
+        s = wave_sum(s);
+        if (lane == 0) {
+            double te = psi_of_count(k - 1) + s / (double)cd.n;
+            if (*err != 0)
+                te = __builtin_nan("");
+            results[cd.result] = te;
+        }
     }
+    if (pv == nullptr)
+        return;
+    // the workgroup that finishes last (done counts finished workgroups, zero at
+    // launch) computes every group's p-value and copies the error word behind them
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0)
+        last = atomicAdd(done, 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (!last)
+        return;
+    __threadfence();
+    for (int g = threadIdx.x; g < n_groups; g += blockDim.x)
+        pv[g] = group_pvalue(results, g, n_surr);
+    if (threadIdx.x == 0 && err_out != nullptr)
+        *err_out = *err;
 }
 
 __global__ void pvalue_kernel(const double *__restrict__ results, int n_groups, int n_surr,
@@ -1055,11 +1091,7 @@ __global__ void pvalue_kernel(const double *__restrict__ results, int n_groups, 
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_groups)
         return;
-    const double *r = results + (int64_t)g * (n_surr + 1);
-    int c = 0;
-    for (int s = 1; s <= n_surr; ++s)
-        c += r[s] >= r[0];
-    pv[g] = n_surr > 0 ? (double)c / (double)n_surr : __builtin_nan("");
+    pv[g] = group_pvalue(results, g, n_surr);
 }
 
 // Delay reconstruction (eq. 5): per window group, the delay whose original
@@ -1227,12 +1259,15 @@ hipError_t launch_check_perms(const int32_t *perms, const int64_t *rows, const i
 }
 
 hipError_t launch_reduce(const ChunkDesc *chunks, int n_chunks, const double *partial, int k,
-                         const int32_t *err, double *results, hipStream_t st)
+                         const int32_t *err, double *results, hipStream_t st, int n_groups, int n_surr,
+                         double *pv, int32_t *done, int32_t *err_out)
 {
     if (n_chunks <= 0)
         return hipSuccess;
+    if (pv != nullptr && done == nullptr)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(reduce_kernel, dim3((n_chunks + 3) / 4), dim3(4 * kWave), 0, st, chunks, n_chunks,
-                       partial, k, err, results);
+                       partial, k, err, results, n_groups, n_surr, pv, done, err_out);
     return hipGetLastError();
 }
 

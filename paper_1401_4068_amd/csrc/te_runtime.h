@@ -46,7 +46,7 @@ struct Batch {
     // byte offsets inside the workspace
     size_t off_coords = 0, off_tables = 0, off_chunks = 0, off_items = 0, off_tasks = 0, off_prow = 0,
            off_prc = 0, off_sorts = 0, off_partial = 0, off_results = 0, off_pv = 0, off_ctr = 0, off_sigma = 0,
-           off_scratch = 0, off_parts = 0, off_qctr = 0;
+           off_scratch = 0, off_parts = 0, off_qctr = 0, off_errout = 0;
     size_t tables_bytes = 0;
     size_t total_bytes = 0;
     std::vector<char> host_tables;

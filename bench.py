@@ -8,10 +8,13 @@ k = 4, float32 data, no surrogates.  One step = the whole hot path (embed,
 k-NN radius search, three range counts, digamma sums) for all 100 windows,
 i.e. 100 TE estimates, with the series already resident in HBM.
 
-The step runs through te_surrogates (batched: one persistent search launch);
-the plain per-window path (te_estimate) is timed beside it.  The JSON line adds
-the search kernel's roofline (FP32 VALU, measured with HIP events around each
-launch) and the CPU oracle timed on the host cores on a bounded sample.
+The timed steps run through te_surrogates_async (batched: one persistent search
+launch per step, queued back to back on one stream, results left in HBM);
+--sync times synchronous te_surrogates calls instead (a host round trip per
+step).  latency_s is the latency of synchronous calls in either mode.  The plain
+per-window path (te_estimate) is timed beside it.  The JSON line adds the search
+kernel's roofline (FP32 VALU, measured with HIP events around each launch) and
+the CPU oracle timed on the host cores on a bounded sample.
 """
 from __future__ import annotations
 
@@ -128,12 +131,20 @@ def batched_record(args, wl, wname):
         tuned = plan.autotune(x, y, perms, ws=ws)
         tuned["tuning_s"] = round(time.perf_counter() - t0, 3)
     stream = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
+    pipelined = not (args.graph or args.sync)
 
     def step():
         return plan.surrogates(x, y, perms, ws=ws, stream=stream, use_graph=args.graph)
 
+    G, S = wl.n_pairs * wl.n_points, wl.n_surrogates
+    dev_out = torch.empty(G * (S + 1) + G, dtype=torch.float64, device="cuda")
+
+    def step_async():
+        # the same hot path queued on the stream: results stay in HBM, no host round trip
+        return plan.surrogates_async(x, y, perms, ws=ws, stream=stream, out=dev_out)
+
     for _ in range(args.warmup):
-        step()
+        step_async() if pipelined else step()
     te.profile_enable(True)
     te.profile_read(reset=True)
     te.profile_work(reset=True)
@@ -142,13 +153,28 @@ def batched_record(args, wl, wname):
     t0 = time.perf_counter()
     for _ in range(args.steps):
         s0 = time.perf_counter()
-        out = step()
+        if pipelined:
+            step_async()
+        else:
+            out = step()
         lat.append(time.perf_counter() - s0)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     k_ms, k_n = te.profile_read(reset=True)
     w1, w2 = te.profile_work(reset=True)
     te.profile_enable(False)
+    if pipelined:
+        # results of the last queued step against a synchronous call (bit for bit), and the
+        # latency of synchronous calls (one call = one step with its host round trip)
+        out = step()
+        got = dev_out.cpu().numpy()
+        assert np.array_equal(got[:G * (S + 1)].reshape(wl.n_pairs, wl.n_points, S + 1)[..., 0], out[0]), \
+            "queued and synchronous calls disagree"
+        lat = []
+        for _ in range(min(args.steps, 20)):
+            s0 = time.perf_counter()
+            step()
+            lat.append(time.perf_counter() - s0)
     est = wl.n_estimates()
     value = est * args.steps / dt
     evals_per_s = 2 * pairs_per_pass * args.steps / dt
@@ -207,7 +233,10 @@ def batched_record(args, wl, wname):
                     windows=wl.n_points, points_per_window_min=int(n.min()), points_per_window_max=int(n.max()),
                     d_y=wl.d_y, d_x=wl.d_x, tau=wl.tau, u=wl.u, dim=D, k=wl.k, surrogates=wl.n_surrogates,
                     estimates_per_step=est, workspace_bytes=int(full),
-                    path="batched (te_surrogates, one persistent search launch)" + (", hipGraph" if args.graph else "")),
+                    path=("batched (te_surrogates_async: one persistent search launch per step, steps queued "
+                          "back to back, results left in HBM)" if pipelined else
+                          "batched (te_surrogates, one persistent search launch)" + (", hipGraph" if args.graph
+                                                                                    else ""))),
         distance_evals_per_s=round(evals_per_s, 1),
         pct_fp32_valu_peak=None if roof is None else round(100 * roof["frac"], 2),
         latency_s=dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99))),
@@ -423,6 +452,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--graph", action="store_true", help="replay the batched step as a hipGraph")
+    ap.add_argument("--sync", action="store_true",
+                    help="time synchronous te_surrogates calls (a host round trip per step) instead of queued steps")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--jobs", type=int, default=60, help="served workload: jobs per trace")
     ap.add_argument("--arena-gb", type=int, default=32, help="served workload: device arena")

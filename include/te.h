@@ -130,6 +130,24 @@ te_status te_surrogates(te_plan plan, const float *x, const float *y, const int3
                         void *ws, size_t ws_bytes, void *hip_stream, int32_t use_graph,
                         double *te_orig, double *te_surr, double *p_value);
 
+/* The batched path of te_surrogates (same searches, same results bit for bit)
+ * enqueued on hip_stream with no host synchronisation, for pipelines that keep
+ * the GPU busy across calls.  Returns once the work is queued.
+ *   x, y, perms  as for te_surrogates; they and ws must stay valid and unchanged
+ *            until the stream has run the work (calls on one stream may reuse ws)
+ *   ws       device workspace of ws_bytes >= the full bytes of
+ *            te_plan_workspace_bytes (TE_ERR_NOMEM otherwise: no batch splitting)
+ *   out      float64 [G (S + 1) + G], G = n_pairs * n_points, S = n_surrogates,
+ *            device memory or pinned host memory (hipHostMalloc), filled in
+ *            stream order: out[g (S + 1)] the original estimate of window group g,
+ *            out[g (S + 1) + 1 + s] surrogate s, out[G (S + 1) + g] its p-value
+ *            (NaN if S == 0).
+ * Invalid input (a non-finite value, an invalid permutation) cannot be reported
+ * through the status here: every estimate and p-value of the call is NaN then.
+ * Destroy the plan only after the stream has finished its calls. */
+te_status te_surrogates_async(te_plan plan, const float *x, const float *y, const int32_t *perms,
+                              void *ws, size_t ws_bytes, void *hip_stream, double *out);
+
 /* Local transfer entropy (the per-point quantity of eq. 17, whose average is
  * the estimate, eq. 18): for every pooled point i of every original window,
  *   lte_i = psi(k) + psi(n_P(i)+1) - psi(n_TP(i)+1) - psi(n_PS(i)+1),

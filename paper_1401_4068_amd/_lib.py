@@ -59,6 +59,7 @@ SIGNATURES = {
     "te_plan_workspace_bytes": ([_vp, _szp, _szp, _szp], _st),
     "te_estimate": ([_vp, _vp, _vp, _vp, _sz, _vp, _dp], _st),
     "te_surrogates": ([_vp, _vp, _vp, _vp, _vp, _sz, _vp, _i32, _dp, _dp, _dp], _st),
+    "te_surrogates_async": ([_vp, _vp, _vp, _vp, _vp, _sz, _vp, _vp], _st),
     "te_knn_counts_workspace_bytes": ([_i32, _i64], _sz),
     "te_profile_enable": ([_i32], _st),
     "te_profile_read": ([_dp, ctypes.POINTER(_i64), _i32], _st),

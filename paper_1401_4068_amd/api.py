@@ -229,6 +229,30 @@ class Plan:
                                   _dp(te_surr) if S > 0 else None, _dp(pv)))
         return te_orig, te_surr, pv
 
+    def surrogates_async(self, x, y, perms=None, ws=None, stream=None, out=None):
+        """te_surrogates_async: the batched path queued on `stream` without waiting.
+        Returns `out`, a CUDA float64 tensor [G * (S + 1) + G] (G = n_pairs * n_points):
+        estimates [G, S + 1] (original first), then p-values [G]; valid once the stream
+        has run the work.  ws must hold the full batch (workspace_bytes()["full"])."""
+        torch = _torch()
+        self._check_series(x, y)
+        S = self.n_surrogates
+        G = self.n_pairs * self.n_points
+        if S > 0:
+            want = self.n_pairs * self.n_points * S * self.shape["n_trials"]
+            if perms is None or perms.numel() != want:
+                raise ValueError("perms must be int32 [n_pairs, n_points, S, n_trials] (%d values)" % want)
+        if out is None:
+            out = torch.empty(G * (S + 1) + G, dtype=torch.float64, device="cuda")
+        elif out.dtype != torch.float64 or out.numel() != G * (S + 1) + G or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor of %d values" % (G * (S + 1) + G))
+        wsp, wsn = self._ws_args(ws)
+        sh, _ = _stream_handle(stream)
+        pp = ctypes.c_void_p(0) if perms is None else _dev_ptr(perms, torch.int32, "perms")
+        check(lib().te_surrogates_async(self._h, _dev_ptr(x, torch.float32, "x"), _dev_ptr(y, torch.float32, "y"),
+                                        pp, wsp, wsn, sh, ctypes.c_void_p(out.data_ptr())))
+        return out
+
 
 class Server:
     """Continuous-batching server (te_serve_*): jobs are submitted with host arrays and

@@ -349,6 +349,8 @@ PinnedPool::~PinnedPool()
 
 Plan::~Plan()
 {
+    if (async_tables)
+        hipHostFree(async_tables);
     for (auto &g : graphs) {
         if (g.exec)
             hipGraphExecDestroy(g.exec);
@@ -384,12 +386,16 @@ int Plan::grid_waves(int64_t n_items) const
 // Enqueue one batch: upload tables, embed, search, reduce, p-values, copy results
 // into the pinned staging block `stage` (results, p-values, error word).
 te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, const int32_t *perms, char *ws,
-                              void *stage, hipStream_t st, double *lte_out, const int32_t *u_dev) const
+                              void *stage, hipStream_t st, double *lte_out, const int32_t *u_dev,
+                              const void *tables_src, void *out_dst) const
 {
     hipError_t e;
     char *tables_host = static_cast<char *>(stage);
-    std::memcpy(tables_host, b.host_tables.data(), b.tables_bytes);
-    e = hipMemcpyAsync(ws + b.off_tables, tables_host, b.tables_bytes, hipMemcpyHostToDevice, st);
+    if (tables_src == nullptr) {
+        std::memcpy(tables_host, b.host_tables.data(), b.tables_bytes);
+        tables_src = tables_host;
+    }
+    e = hipMemcpyAsync(ws + b.off_tables, tables_src, b.tables_bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess)
         return hip_fail(e, "upload tables");
     // ctr: [1] error word, [2] finished reduce workgroups; the queue counters follow
@@ -443,9 +449,11 @@ te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, co
     if ((e = launch_reduce(a.chunks, a.n_chunks, a.partial, p.k, ctr + 1, res, st, b.n_groups, b.n_surr, pv, ctr + 2,
                            err_out)) != hipSuccess)
         return hip_fail(e, "reduce launch");
-    char *out = tables_host + align_up(b.tables_bytes, 256);
-    e = hipMemcpyAsync(out, res, sizeof(double) * (b.n_results + b.n_groups) + sizeof(int32_t), hipMemcpyDeviceToHost,
-                       st);
+    if (out_dst != nullptr)
+        e = hipMemcpyAsync(out_dst, res, sizeof(double) * (b.n_results + b.n_groups), hipMemcpyDefault, st);
+    else
+        e = hipMemcpyAsync(tables_host + align_up(b.tables_bytes, 256), res,
+                           sizeof(double) * (b.n_results + b.n_groups) + sizeof(int32_t), hipMemcpyDeviceToHost, st);
     if (e != hipSuccess)
         return hip_fail(e, "download results");
     return TE_OK;
@@ -625,6 +633,21 @@ te_status te_surrogates(te_plan plan, const float *x, const float *y, const int3
         return s;
     return plan->impl.run_surrogates(x, y, perms, static_cast<char *>(ws), ws_bytes, (hipStream_t)hip_stream,
                                      use_graph != 0, te_orig, te_surr, p_value);
+}
+
+te_status te_surrogates_async(te_plan plan, const float *x, const float *y, const int32_t *perms, void *ws,
+                              size_t ws_bytes, void *hip_stream, double *out)
+{
+    clear_error();
+    if (!plan || !x || !y || !ws || !out)
+        return fail(TE_ERR_INVALID, "null argument");
+    const Plan &P = plan->impl;
+    if (P.p.n_surrogates > 0 && !perms)
+        return fail(TE_ERR_INVALID, "n_surrogates > 0 needs perms");
+    te_status s = P.ensure_device();
+    if (s != TE_OK)
+        return s;
+    return P.run_surrogates_async(x, y, perms, static_cast<char *>(ws), ws_bytes, (hipStream_t)hip_stream, out);
 }
 
 te_status te_plan_local_offsets(te_plan plan, int64_t *offsets)

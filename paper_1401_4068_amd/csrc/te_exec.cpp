@@ -197,6 +197,30 @@ te_status Plan::run_surrogates(const float *x, const float *y, const int32_t *pe
     return s;
 }
 
+// The full batch enqueued on the stream with no host round trip: tables from a
+// pinned copy that never changes after it is made, results copied to `out`.
+te_status Plan::run_surrogates_async(const float *x, const float *y, const int32_t *perms, char *ws,
+                                     size_t ws_bytes, hipStream_t st, double *out) const
+{
+    if (ws_bytes < full.total_bytes)
+        return fail(TE_ERR_NOMEM, "te_surrogates_async needs the full workspace (%zu bytes), got %zu",
+                    full.total_bytes, ws_bytes);
+    const void *tables = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(async_mu);
+        if (!async_tables) {
+            void *h = nullptr;
+            hipError_t e = hipHostMalloc(&h, std::max<size_t>(full.tables_bytes, 64), hipHostMallocDefault);
+            if (e != hipSuccess)
+                return hip_fail(e, "hipHostMalloc (tables)");
+            std::memcpy(h, full.host_tables.data(), full.tables_bytes);
+            async_tables = h;
+        }
+        tables = async_tables;
+    }
+    return enqueue_batch(full, x, y, perms, ws, nullptr, st, nullptr, nullptr, tables, out);
+}
+
 // Local TE: the originals of every window in one batch, per-point terms written
 // through the sort maps to window order.
 te_status Plan::run_local(const float *x, const float *y, char *ws, size_t ws_bytes, hipStream_t st, double *lte,

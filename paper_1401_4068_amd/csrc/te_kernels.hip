@@ -1079,8 +1079,9 @@ __global__ void reduce_kernel(const ChunkDesc *__restrict__ chunks, int n_chunks
     if (!last)
         return;
     __threadfence();
+    const bool bad = *err != 0;
     for (int g = threadIdx.x; g < n_groups; g += blockDim.x)
-        pv[g] = group_pvalue(results, g, n_surr);
+        pv[g] = bad ? __builtin_nan("") : group_pvalue(results, g, n_surr);
     if (threadIdx.x == 0 && err_out != nullptr)
         *err_out = *err;
 }

@@ -102,6 +102,8 @@ struct Plan {
     size_t plain_bytes = 0;
 
     mutable PinnedPool pool;
+    mutable std::mutex async_mu;
+    mutable void *async_tables = nullptr;  // pinned, immutable copy of full.host_tables (te_surrogates_async)
     mutable std::mutex graph_mu;
     mutable std::vector<GraphEntry> graphs;
 
@@ -112,9 +114,15 @@ struct Plan {
     te_status build_group_batch(const std::vector<int> &groups, int n_surr, Batch *b,
                                 const BatchOptions &opt = BatchOptions()) const;
     int grid_waves(int64_t n_items) const;
+    // tables_src: upload the tables from this pinned copy instead of through `stage`;
+    // out_dst: copy the results block (estimates [group][original, surrogates], then
+    // p-values) there (device or pinned host) instead of into `stage`.
     te_status enqueue_batch(const Batch &b, const float *x, const float *y, const int32_t *perms, char *ws,
                             void *stage, hipStream_t st, double *lte_out = nullptr,
-                            const int32_t *u_dev = nullptr) const;
+                            const int32_t *u_dev = nullptr, const void *tables_src = nullptr,
+                            void *out_dst = nullptr) const;
+    te_status run_surrogates_async(const float *x, const float *y, const int32_t *perms, char *ws, size_t ws_bytes,
+                                   hipStream_t st, double *out) const;
     size_t scan_bytes(const std::vector<int> &groups, const std::vector<int32_t> &delays) const;
     te_status run_scan(const float *x, const float *y, const int32_t *perms, const std::vector<int32_t> &delays,
                        char *ws, size_t ws_bytes, hipStream_t st, double *te_scan, int32_t *u_best,

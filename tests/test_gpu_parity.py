@@ -202,6 +202,56 @@ def test_graph_replay_matches_eager(te):
         assert torch.isfinite(z)
 
 
+def _async_split(plan, a):
+    G, S = plan.n_pairs * plan.n_points, plan.n_surrogates
+    est = a[:G * (S + 1)].reshape(plan.n_pairs, plan.n_points, S + 1)
+    return est[..., 0], est[..., 1:], a[G * (S + 1):].reshape(plan.n_pairs, plan.n_points)
+
+
+def test_async_matches_batched(te):
+    import torch
+    wl = synth.uneven_surrogates(R=150, T=60, n_points=4, n_surrogates=3, n_lo=300, n_hi=1500)
+    x, y, perms = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    t0, ts, pv = plan.surrogates(x, y, perms)
+    G, S = plan.n_pairs * plan.n_points, plan.n_surrogates
+    s = torch.cuda.Stream()
+    ws = plan.workspace()
+    say("async: three calls back to back on one workspace, then one into pinned host memory")
+    outs = [plan.surrogates_async(x, y, perms, ws=ws, stream=s) for _ in range(3)]
+    host = torch.empty(G * (S + 1) + G, dtype=torch.float64).pin_memory()
+    plan.surrogates_async(x, y, perms, ws=ws, stream=s, out=host)
+    s.synchronize()
+    for o in outs + [host]:
+        a0, a1, a2 = _async_split(plan, o.cpu().numpy())
+        np.testing.assert_array_equal(a0, t0)
+        np.testing.assert_array_equal(a1, ts)
+        np.testing.assert_array_equal(a2, pv)
+    full, mn, _ = plan.workspace_bytes()
+    assert mn < full
+    with pytest.raises(te.TEError) as ei:
+        plan.surrogates_async(x, y, perms, ws=torch.empty(mn, dtype=torch.uint8, device="cuda"))
+    assert ei.value.status == 2
+
+
+def test_async_without_surrogates_and_invalid_input(te):
+    import torch
+    wl = synth.generic((15,), R=30, T=40, starts=(20,), windows=(10,))
+    x, y, _ = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    t0, _, _ = plan.surrogates(x, y)
+    out = plan.surrogates_async(x, y)
+    torch.cuda.synchronize()
+    a0, a1, a2 = _async_split(plan, out.cpu().numpy())
+    np.testing.assert_array_equal(a0, t0)
+    assert a1.size == 0 and np.isnan(a2).all()
+    wl.y[0, 3, 25] = np.nan                                 # target future of point (3, 25)
+    x, y, _ = dev(wl)
+    out = plan.surrogates_async(x, y)
+    torch.cuda.synchronize()
+    assert np.isnan(out.cpu().numpy()).all()
+
+
 def test_runs_are_bitwise_reproducible(te):
     wl = synth.uneven_surrogates(R=150, T=60, n_points=4, n_surrogates=3, n_lo=300, n_hi=1500)
     x, y, perms = dev(wl)

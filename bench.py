@@ -244,9 +244,38 @@ def batched_record(args, wl, wname):
         tuned_shape=tuned,
         roofline=roof,
     )
+    if pipelined and not args.no_two_stream:
+        rec["pipelined_two_streams"] = two_stream_record(plan, wl, x, y, perms, ws, dev_out, args.steps)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl)
     return rec
+
+
+def two_stream_record(plan, wl, x, y, perms, ws, out, steps):
+    """The same queued steps alternating over two streams, each with its own workspace
+    and output buffer: a step's search launch then fills the tail of the previous one.
+    Reported beside `value` (which, with the roofline, is measured on one stream, where
+    each launch runs alone)."""
+    import torch
+    wss = [ws, plan.workspace()]
+    outs = [out, torch.empty_like(out)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+
+    def run(n):
+        for i in range(n):
+            plan.surrogates_async(x, y, perms, ws=wss[i % 2], stream=streams[i % 2], out=outs[i % 2])
+
+    run(4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ref = outs[(steps - 1) % 2].cpu().numpy()
+    other = outs[steps % 2].cpu().numpy()
+    assert np.array_equal(ref, other, equal_nan=True), "the two streams' results disagree"
+    return dict(value=round(wl.n_estimates() * steps / dt, 2), unit="estimates/s",
+                ms_per_step=round(dt / steps * 1e3, 4), streams=2, steps=steps)
 
 
 def scan_record(args, scenario):
@@ -452,6 +481,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--graph", action="store_true", help="replay the batched step as a hipGraph")
+    ap.add_argument("--no-two-stream", action="store_true",
+                    help="skip the two-stream pipelined measurement (profiled runs: its launches overlap)")
     ap.add_argument("--sync", action="store_true",
                     help="time synchronous te_surrogates calls (a host round trip per step) instead of queued steps")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")

@@ -234,6 +234,27 @@ def test_async_matches_batched(te):
     assert ei.value.status == 2
 
 
+def test_async_two_streams_share_a_plan(te):
+    import torch
+    wl = synth.uneven_surrogates(R=120, T=60, n_points=3, n_surrogates=4, n_lo=200, n_hi=1500)
+    x, y, perms = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    t0, ts, pv = plan.surrogates(x, y, perms)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    wss = [plan.workspace(), plan.workspace()]
+    G, S = plan.n_pairs * plan.n_points, plan.n_surrogates
+    outs = [torch.empty(G * (S + 1) + G, dtype=torch.float64, device="cuda") for _ in range(2)]
+    say("async: 10 calls alternating over two streams and workspaces")
+    for i in range(10):
+        plan.surrogates_async(x, y, perms, ws=wss[i % 2], stream=streams[i % 2], out=outs[i % 2])
+    torch.cuda.synchronize()
+    for o in outs:
+        a0, a1, a2 = _async_split(plan, o.cpu().numpy())
+        np.testing.assert_array_equal(a0, t0)
+        np.testing.assert_array_equal(a1, ts)
+        np.testing.assert_array_equal(a2, pv)
+
+
 def test_async_without_surrogates_and_invalid_input(te):
     import torch
     wl = synth.generic((15,), R=30, T=40, starts=(20,), windows=(10,))

@@ -479,8 +479,8 @@ def served_record(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="nonlinear",
                     choices=["nonlinear", "linear", "uneven", "meg", "served", "ar0", "ar1", "ar2", "ar3"],
                     help="ar0: delay recovery against the amount of data; ar1-ar3: the AR coupling scenarios")

@@ -131,3 +131,23 @@ def test_conditioning_needs_room_in_the_target_past():
     assert "d_y <= 3" in str(ei.value)
     with pytest.raises(te.TEError):
         _plan(cond_source=2)
+
+
+def test_async_rejects_missing_arguments_without_gpu():
+    """te_surrogates_async checks its arguments before it touches the device."""
+    from paper_1401_4068_amd import _lib
+    _lib_or_build()
+    L = _lib.lib()
+    p = _plan(n_surrogates=3)
+    dummy = ctypes.c_void_p(1 << 20)                 # never dereferenced: the calls fail first
+    null = ctypes.c_void_p(0)
+    cases = [
+        (null, dummy, dummy, dummy, dummy, dummy),   # no plan
+        (p._h, null, dummy, dummy, dummy, dummy),    # no x
+        (p._h, dummy, dummy, dummy, dummy, null),    # no out
+        (p._h, dummy, dummy, null, dummy, dummy),    # surrogates without perms
+    ]
+    for plan, x, y, perms, ws, out in cases:
+        st = L.te_surrogates_async(plan, x, y, perms, ws, 1 << 20, null, out)
+        assert st == 1, st
+        assert L.te_last_error() is not None

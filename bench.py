@@ -42,7 +42,7 @@ PEAK_FP32_HEADLINE = 157.3                                   # AMD headline (pac
 # HBM bytes per search launch of this workload from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs, scaled by a
 # plain 256 MiB copy (factors 2.000 and 1.000), keyed by the kernel source they were taken on; any other kernel
 # source reports null.
-RECORDED_TRAFFIC = {"096489e9e4b0": 8783.56 * 1024 * 2.0 + 1319.71 * 1024 * 1.0}
+RECORDED_TRAFFIC = {"152d275deeea": 8918.05 * 1024 * 2.0 + 1319.97 * 1024 * 1.0}
 KERNEL_SRC = os.path.join(ROOT, "paper_1401_4068_amd", "csrc", "te_kernels.hip")
 
 

@@ -120,8 +120,9 @@ hipError_t launch_check_perms(const int32_t *perms, const int64_t *rows, const i
 hipError_t launch_search(const SearchArgs &a, int d_y, int d_x, const SearchConfig &cfg, int grid_waves,
                          hipStream_t st);
 // With pv != nullptr the launch also computes the n_groups p-values (results laid
-// out [group][original, surrogates...]) in its last-finishing workgroup, counted on
-// `done` (zero before the launch), and copies *err to *err_out when that is given.
+// out [group][original, surrogates...]; NaN when *err is set) and copies *err to
+// *err_out when that is given: in its last-finishing workgroup, counted on `done`
+// (zero before the launch), for small grids, else in a second kernel.
 hipError_t launch_reduce(const ChunkDesc *chunks, int n_chunks, const double *partial, int k,
                          const int32_t *err, double *results, hipStream_t st, int n_groups = 0, int n_surr = 0,
                          double *pv = nullptr, int32_t *done = nullptr, int32_t *err_out = nullptr);

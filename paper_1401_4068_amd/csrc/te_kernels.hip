@@ -1087,12 +1087,14 @@ __global__ void reduce_kernel(const ChunkDesc *__restrict__ chunks, int n_chunks
 }
 
 __global__ void pvalue_kernel(const double *__restrict__ results, int n_groups, int n_surr,
-                              double *__restrict__ pv)
+                              double *__restrict__ pv, const int32_t *err, int32_t *err_out)
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g == 0 && err_out != nullptr)
+        *err_out = *err;
     if (g >= n_groups)
         return;
-    pv[g] = group_pvalue(results, g, n_surr);
+    pv[g] = (err != nullptr && *err != 0) ? __builtin_nan("") : group_pvalue(results, g, n_surr);
 }
 
 // Delay reconstruction (eq. 5): per window group, the delay whose original
@@ -1267,8 +1269,18 @@ hipError_t launch_reduce(const ChunkDesc *chunks, int n_chunks, const double *pa
         return hipSuccess;
     if (pv != nullptr && done == nullptr)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(reduce_kernel, dim3((n_chunks + 3) / 4), dim3(4 * kWave), 0, st, chunks, n_chunks,
-                       partial, k, err, results, n_groups, n_surr, pv, done, err_out);
+    // the p-values ride on the reduce's last workgroup while the grid is small; above
+    // that, every workgroup's device-scope fence and counter atomic cost more than a
+    // separate launch (about 1 ms for 16 000 workgroups)
+    const int blocks = (n_chunks + 3) / 4;
+    const bool fuse = pv != nullptr && blocks <= 256;
+    hipLaunchKernelGGL(reduce_kernel, dim3(blocks), dim3(4 * kWave), 0, st, chunks, n_chunks, partial, k, err,
+                       results, n_groups, n_surr, fuse ? pv : nullptr, done, err_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || pv == nullptr || fuse)
+        return e;
+    hipLaunchKernelGGL(pvalue_kernel, dim3((std::max(n_groups, 1) + 127) / 128), dim3(128), 0, st, results, n_groups,
+                       n_surr, pv, err, err_out);
     return hipGetLastError();
 }
 
@@ -1277,7 +1289,7 @@ hipError_t launch_pvalues(const double *results, int n_groups, int n_surr, doubl
     if (n_groups <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(pvalue_kernel, dim3((n_groups + 127) / 128), dim3(128), 0, st, results, n_groups,
-                       n_surr, pv);
+                       n_surr, pv, nullptr, nullptr);
     return hipGetLastError();
 }
 

@@ -298,7 +298,9 @@ te_status te_plan_autotune(te_plan plan, const float *x, const float *y, const i
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         return P.npts[a % P.p.n_points] > P.npts[b % P.p.n_points];
     });
-    const int64_t want_items = (int64_t)4 * P.dev.n_cu * 32;
+    // at least 16 items per wave at full occupancy (or the whole batch): with fewer,
+    // the subset's tail favours lower occupancies than the full batch wants
+    const int64_t want_items = (int64_t)16 * P.dev.n_cu * 32;
     std::vector<int> groups;
     Batch b;
     for (int g : order) {
@@ -345,6 +347,8 @@ te_status te_plan_autotune(te_plan plan, const float *x, const float *y, const i
                 P.cfg = SearchConfig{sl, wpg, wg};
                 double tmin = 1e30;
                 for (int rep = 0; rep < 5 && s == TE_OK && e == hipSuccess; ++rep) {
+                    if (rep == 3 && tmin > 20.0)             // long runs: one warm-up and two timed
+                        break;
                     e = hipEventRecord(e0, st);
                     if (e == hipSuccess)
                         s = P.enqueue_batch(b, x, y, perms, ws, stg, st);

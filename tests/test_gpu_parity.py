@@ -255,6 +255,32 @@ def test_async_two_streams_share_a_plan(te):
         np.testing.assert_array_equal(a2, pv)
 
 
+def test_large_batch_pvalues_in_their_own_kernel(te):
+    """Over 1 024 chunks the p-values (and the error word) come from a kernel of their own."""
+    import torch
+    wl = synth.uneven_surrogates(R=100, T=60, n_points=6, n_surrogates=200, n_lo=100, n_hi=600)
+    assert wl.n_pairs * wl.n_points * (wl.n_surrogates + 1) > 1024
+    x, y, perms = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    t0, ts, pv = plan.surrogates(x, y, perms)
+    say("large batch", wl.chunk_sizes().min(), wl.chunk_sizes().max())
+    _compare(wl, t0, ts, pv)
+    out = plan.surrogates_async(x, y, perms)
+    torch.cuda.synchronize()
+    a0, a1, a2 = _async_split(plan, out.cpu().numpy())
+    np.testing.assert_array_equal(a0, t0)
+    np.testing.assert_array_equal(a1, ts)
+    np.testing.assert_array_equal(a2, pv)
+    # invalid input: an error on the synchronous path, all NaN on the queued one
+    wl.y[0, 3, int(wl.window_start[0]) + 1] = np.nan
+    x, y, perms = dev(wl)
+    with pytest.raises(te.TEError):
+        plan.surrogates(x, y, perms)
+    out = plan.surrogates_async(x, y, perms)
+    torch.cuda.synchronize()
+    assert np.isnan(out.cpu().numpy()).all()
+
+
 def test_async_without_surrogates_and_invalid_input(te):
     import torch
     wl = synth.generic((15,), R=30, T=40, starts=(20,), windows=(10,))

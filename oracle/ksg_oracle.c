@@ -113,6 +113,48 @@ static double maxnorm(const float *p, const float *q, int lo, int hi, int mode)
     return m;
 }
 
+/* Radius and the three strict counts of reference point i of one chunk, by
+ * brute force over all j != i (O(N D)).  best: scratch of k doubles. */
+static void point_stats(const float *pts, int N, int d_y, int d_x, int k, int mode, int i,
+                        double *best, double *eps, int32_t *n_p, int32_t *n_tp, int32_t *n_ps)
+{
+    const int D = 1 + d_y + d_x;
+    const float *pi = pts + (size_t)i * D;
+    /* k smallest joint distances, kept sorted ascending */
+    for (int s = 0; s < k; ++s)
+        best[s] = INFINITY;
+    for (int j = 0; j < N; ++j) {
+        if (j == i)
+            continue;
+        const double d = maxnorm(pi, pts + (size_t)j * D, 0, D, mode);
+        if (d < best[k - 1]) {
+            int s = k - 1;
+            while (s > 0 && best[s - 1] > d) {
+                best[s] = best[s - 1];
+                --s;
+            }
+            best[s] = d;
+        }
+    }
+    const double e = best[k - 1];
+    int32_t cp = 0, ctp = 0, cps = 0;
+    for (int j = 0; j < N; ++j) {
+        if (j == i)
+            continue;
+        const float *pj = pts + (size_t)j * D;
+        if (maxnorm(pi, pj, 1, 1 + d_y, mode) < e)          /* P  */
+            ++cp;
+        if (maxnorm(pi, pj, 0, 1 + d_y, mode) < e)          /* TP */
+            ++ctp;
+        if (maxnorm(pi, pj, 1, D, mode) < e)                /* PS */
+            ++cps;
+    }
+    *eps = e;
+    *n_p = cp;
+    *n_tp = ctp;
+    *n_ps = cps;
+}
+
 /* Radius and the three strict counts for every point of one chunk.
  *   pts    float32 [N][D], D = 1 + d_y + d_x, coordinates ordered (T | P | S)
  *   eps    out [N]: distance to the k-th nearest neighbour in the joint space
@@ -122,50 +164,99 @@ static double maxnorm(const float *p, const float *q, int lo, int hi, int mode)
 int ksg_counts(const float *pts, int N, int d_y, int d_x, int k, int mode,
                double *eps, int32_t *n_p, int32_t *n_tp, int32_t *n_ps)
 {
-    const int D = 1 + d_y + d_x;
     if (k < 1 || N <= k)
         return -1;
     double *best = (double *)malloc(sizeof(double) * (size_t)k);
     if (!best)
         return -1;
-    for (int i = 0; i < N; ++i) {
-        const float *pi = pts + (size_t)i * D;
-        /* k smallest joint distances, kept sorted ascending */
-        for (int s = 0; s < k; ++s)
-            best[s] = INFINITY;
-        for (int j = 0; j < N; ++j) {
-            if (j == i)
-                continue;
-            const double d = maxnorm(pi, pts + (size_t)j * D, 0, D, mode);
-            if (d < best[k - 1]) {
-                int s = k - 1;
-                while (s > 0 && best[s - 1] > d) {
-                    best[s] = best[s - 1];
-                    --s;
-                }
-                best[s] = d;
-            }
-        }
-        const double e = best[k - 1];
-        int32_t cp = 0, ctp = 0, cps = 0;
-        for (int j = 0; j < N; ++j) {
-            if (j == i)
-                continue;
-            const float *pj = pts + (size_t)j * D;
-            if (maxnorm(pi, pj, 1, 1 + d_y, mode) < e)          /* P  */
-                ++cp;
-            if (maxnorm(pi, pj, 0, 1 + d_y, mode) < e)          /* TP */
-                ++ctp;
-            if (maxnorm(pi, pj, 1, D, mode) < e)                /* PS */
-                ++cps;
-        }
-        eps[i] = e;
-        n_p[i] = cp;
-        n_tp[i] = ctp;
-        n_ps[i] = cps;
-    }
+    for (int i = 0; i < N; ++i)
+        point_stats(pts, N, d_y, d_x, k, mode, i, best, eps + i, n_p + i, n_tp + i, n_ps + i);
     free(best);
     return 0;
+}
+
+/* The same statistics for the listed reference points only: entry q of the
+ * outputs belongs to point idx[q] (each O(N D), so single points of very large
+ * chunks can be checked).  Returns 0, or -1 if N <= k, k < 1 or an index is
+ * outside [0, N). */
+int ksg_counts_points(const float *pts, int N, int d_y, int d_x, int k, int mode,
+                      const int64_t *idx, int n_idx,
+                      double *eps, int32_t *n_p, int32_t *n_tp, int32_t *n_ps)
+{
+    if (k < 1 || N <= k)
+        return -1;
+    for (int q = 0; q < n_idx; ++q)
+        if (idx[q] < 0 || idx[q] >= N)
+            return -1;
+    double *best = (double *)malloc(sizeof(double) * (size_t)k);
+    if (!best)
+        return -1;
+    for (int q = 0; q < n_idx; ++q)
+        point_stats(pts, N, d_y, d_x, k, mode, (int)idx[q], best, eps + q, n_p + q, n_tp + q, n_ps + q);
+    free(best);
+    return 0;
+}
+
+/* ksg_counts with the reference points split over threads: thread t takes the
+ * contiguous range of points [t N / n, (t+1) N / n).  Every point's statistics
+ * come from the same brute-force loop, so the result is that of ksg_counts. */
+typedef struct {
+    const float *pts;
+    int N, d_y, d_x, k, mode, i0, i1;
+    double *eps;
+    int32_t *n_p, *n_tp, *n_ps;
+    int status;
+} split_t;
+
+static void *split_worker(void *arg)
+{
+    split_t *a = (split_t *)arg;
+    double *best = (double *)malloc(sizeof(double) * (size_t)a->k);
+    if (!best) {
+        a->status = -1;
+        return NULL;
+    }
+    for (int i = a->i0; i < a->i1; ++i)
+        point_stats(a->pts, a->N, a->d_y, a->d_x, a->k, a->mode, i, best, a->eps + i, a->n_p + i,
+                    a->n_tp + i, a->n_ps + i);
+    free(best);
+    a->status = 0;
+    return NULL;
+}
+
+int ksg_counts_split(const float *pts, int N, int d_y, int d_x, int k, int mode, int n_threads,
+                     double *eps, int32_t *n_p, int32_t *n_tp, int32_t *n_ps)
+{
+    if (k < 1 || N <= k)
+        return -1;
+    if (n_threads <= 0)
+        n_threads = (int)sysconf(_SC_NPROCESSORS_ONLN);
+    if (n_threads > N)
+        n_threads = N;
+    split_t *parts = (split_t *)calloc((size_t)n_threads, sizeof(split_t));
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)n_threads);
+    if (!parts || !th) {
+        free(parts);
+        free(th);
+        return -1;
+    }
+    for (int t = 0; t < n_threads; ++t) {
+        split_t *a = &parts[t];
+        a->pts = pts; a->N = N; a->d_y = d_y; a->d_x = d_x; a->k = k; a->mode = mode;
+        a->i0 = (int)((int64_t)t * N / n_threads);
+        a->i1 = (int)((int64_t)(t + 1) * N / n_threads);
+        a->eps = eps; a->n_p = n_p; a->n_tp = n_tp; a->n_ps = n_ps;
+        a->status = -1;
+        pthread_create(&th[t], NULL, split_worker, a);
+    }
+    int bad = 0;
+    for (int t = 0; t < n_threads; ++t) {
+        pthread_join(th[t], NULL);
+        bad |= parts[t].status != 0;
+    }
+    free(parts);
+    free(th);
+    return bad ? -1 : 0;
 }
 
 /* ------------------------------------------------------------- estimator */

@@ -46,6 +46,10 @@ def lib():
         L.ksg_embed.restype = ci
         L.ksg_counts.argtypes = [f32p, ci, ci, ci, ci, ci, f64p, i32p, i32p, i32p]
         L.ksg_counts.restype = ci
+        L.ksg_counts_points.argtypes = [f32p, ci, ci, ci, ci, ci, i64p, ci, f64p, i32p, i32p, i32p]
+        L.ksg_counts_points.restype = ci
+        L.ksg_counts_split.argtypes = [f32p, ci, ci, ci, ci, ci, ci, f64p, i32p, i32p, i32p]
+        L.ksg_counts_split.restype = ci
         L.ksg_digamma_int.argtypes = [ci]
         L.ksg_digamma_int.restype = ctypes.c_double
         L.ksg_te_from_counts.argtypes = [i32p, i32p, i32p, ci, ci]
@@ -95,17 +99,40 @@ def embed(x, y, d_y, d_x, tau, u, w, W, Rc=None, src_perm=None, tgt_perm=None, c
     return out
 
 
-def counts(pts, d_y, d_x, k, mode=0):
-    """(eps float64 [N], counts int32 [3, N] as (n_P, n_TP, n_PS)) of one chunk [N, D]."""
+def counts(pts, d_y, d_x, k, mode=0, n_threads=1):
+    """(eps float64 [N], counts int32 [3, N] as (n_P, n_TP, n_PS)) of one chunk [N, D].
+
+    n_threads != 1 splits the reference points of the chunk into contiguous ranges
+    over that many threads (0: all online cores); the result is the same."""
     pts = np.ascontiguousarray(pts, np.float32)
     N = pts.shape[0]
     eps = np.empty(N, np.float64)
     cnt = np.empty((3, N), np.int32)
-    st = lib().ksg_counts(_p(pts, ctypes.c_float), N, d_y, d_x, k, mode, _p(eps, ctypes.c_double),
-                          _p(cnt[0], ctypes.c_int32), _p(cnt[1], ctypes.c_int32),
-                          _p(cnt[2], ctypes.c_int32))
+    args = (_p(eps, ctypes.c_double), _p(cnt[0], ctypes.c_int32), _p(cnt[1], ctypes.c_int32),
+            _p(cnt[2], ctypes.c_int32))
+    if n_threads == 1:
+        st = lib().ksg_counts(_p(pts, ctypes.c_float), N, d_y, d_x, k, mode, *args)
+    else:
+        st = lib().ksg_counts_split(_p(pts, ctypes.c_float), N, d_y, d_x, k, mode, int(n_threads), *args)
     if st != 0:
         raise ValueError("need k >= 1 and N > k")
+    return eps, cnt
+
+
+def counts_points(pts, d_y, d_x, k, idx, mode=0):
+    """Radius and counts of the listed reference points only (each by brute force over
+    the whole chunk): (eps float64 [len(idx)], counts int32 [3, len(idx)])."""
+    pts = np.ascontiguousarray(pts, np.float32)
+    idx = np.ascontiguousarray(idx, np.int64)
+    N = pts.shape[0]
+    n = idx.shape[0]
+    eps = np.empty(n, np.float64)
+    cnt = np.empty((3, n), np.int32)
+    st = lib().ksg_counts_points(_p(pts, ctypes.c_float), N, d_y, d_x, k, mode, _p(idx, ctypes.c_int64), n,
+                                 _p(eps, ctypes.c_double), _p(cnt[0], ctypes.c_int32), _p(cnt[1], ctypes.c_int32),
+                                 _p(cnt[2], ctypes.c_int32))
+    if st != 0:
+        raise ValueError("need k >= 1, N > k and indices in [0, N)")
     return eps, cnt
 
 

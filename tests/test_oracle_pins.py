@@ -83,6 +83,53 @@ def test_oracle_matches_exhaustive_search(kind, d_y, d_x):
         assert te == pytest.approx(float(tiny.te_exact_minus_gamma_free(c2, k)), abs=1e-13)
 
 
+@pytest.mark.parametrize("kind", ["gauss", "grid", "dups"])
+def test_counts_split_over_threads_equal_the_single_thread_call(kind):
+    """ksg_counts_split (reference points cut into contiguous ranges, one per thread) gives
+    the single-thread result bit for bit, for thread counts that do and do not divide N,
+    and for more threads than points."""
+    for N, D, d_y, d_x, k in ((9, 3, 1, 1, 2), (301, 7, 3, 3, 4), (1000, 9, 4, 4, 4)):
+        pts = _random_points(derive_key(53, N, hash(kind) & 0xFFFF), N, D, kind)
+        e1, c1 = oracle.counts(pts, d_y, d_x, k)
+        for threads in (2, 3, 7, 16, N + 5):
+            e2, c2 = oracle.counts(pts, d_y, d_x, k, n_threads=threads)
+            np.testing.assert_array_equal(e1, e2)
+            np.testing.assert_array_equal(c1, c2)
+
+
+def test_counts_of_listed_points_equal_the_whole_chunk_and_brute_force():
+    pts = _random_points(derive_key(54), 60, 5, "grid")
+    e1, c1 = oracle.counts(pts, 2, 2, 3)
+    idx = np.array([0, 59, 17, 17, 3], np.int64)
+    e2, c2 = oracle.counts_points(pts, 2, 2, 3, idx)
+    np.testing.assert_array_equal(e2, e1[idx])
+    np.testing.assert_array_equal(c2, c1[:, idx])
+    e3, c3, _ = tiny.neighbours(pts, 2, 2, 3)            # exhaustive pure-Python search
+    np.testing.assert_array_equal(e2, e3[idx])
+    np.testing.assert_array_equal(c2, c3[:, idx])
+    with pytest.raises(ValueError):
+        oracle.counts_points(pts, 2, 2, 3, np.array([60], np.int64))
+
+
+def test_counts_batch_offsets_and_strides():
+    """ksg_counts_batch (chunks of mixed sizes in one concatenated array, threaded over chunks)
+    gives every chunk's single-chunk result, and the exhaustive search's on the small ones."""
+    sizes = [5, 64, 1, 33, 700, 2]
+    kinds = ["gauss", "grid", "dups", "fine", "gauss", "grid"]
+    chunks = [_random_points(derive_key(55, i), n + 4, 6, kind) for i, (n, kind) in enumerate(zip(sizes, kinds))]
+    for threads in (1, 3, 0):
+        got = oracle.counts_batch(chunks, 2, 3, 4, n_threads=threads)
+        assert len(got) == len(chunks)
+        for ch, (e, c) in zip(chunks, got):
+            e1, c1 = oracle.counts(ch, 2, 3, 4)
+            np.testing.assert_array_equal(e, e1)
+            np.testing.assert_array_equal(c, c1)
+            if ch.shape[0] <= 70:
+                e2, c2, _ = tiny.neighbours(ch, 2, 3, 4)
+                np.testing.assert_array_equal(e, e2)
+                np.testing.assert_array_equal(c, c2)
+
+
 def test_strict_inside_joint_ball_is_counted_everywhere():
     pts = _random_points(derive_key(7), 50, 7, "gauss")
     eps, cnt = oracle.counts(pts, 3, 3, 4)

@@ -1,20 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark: ensemble transfer-entropy estimates per second on one MI355X.
 
-Workload (the plain GPU ensemble configuration): nonlinear coupled AR pair,
-500 trials x 300 samples; 100 analysis windows of 10 samples, each pooling all
-trials (N = 5000 points), d_y = d_x = 3, tau = 1, u = 3 (joint dimension 7),
-k = 4, float32 data, no surrogates.  One step = the whole hot path (embed,
-k-NN radius search, three range counts, digamma sums) for all 100 windows,
-i.e. 100 TE estimates, with the series already resident in HBM.
+Default workload (batched surrogates): linear coupled AR pair, 5000 trials x 400
+samples; 60 analysis time points whose windows pool 1 014 to 49 400 points
+(R_c trials x W_c samples, uneven), d_y = d_x = 3, tau = 1, u = 1 (joint
+dimension 7), k = 4, float32 data, 200 trial-shuffled source surrogates per time
+point: 12 060 estimates per step.  One step = the whole hot path on device-
+resident series: the surrogate permutations drawn from the plan's seed, sorting
+and embedding every window, the k-NN radius search, the three range counts, the
+digamma sums and the p-values of all 60 x 201 chunks, in one persistent search
+launch (te_surrogates_async, steps queued back to back on one stream).
 
-The timed steps run through te_surrogates_async (batched: one persistent search
-launch per step, queued back to back on one stream, results left in HBM);
---sync times synchronous te_surrogates calls instead (a host round trip per
-step).  latency_s is the latency of synchronous calls in either mode.  The plain
-per-window path (te_estimate) is timed beside it.  The JSON line adds the search
-kernel's roofline (FP32 VALU, measured with HIP events around each launch) and
-the CPU oracle timed on the host cores on a bounded sample.
+The JSON line adds the search kernel's roofline (FP32 VALU; kernel time from HIP
+events around every timed launch, evaluated pairs from device counters in a
+separate untimed step), the plain per-time-point path on the same work, and the
+CPU oracle timed on the host cores on a bounded sample.  --workload selects the
+other configurations (nonlinear ensemble without surrogates, MEG-shaped batch,
+linear pair, AR delay scans, served mix).
 """
 from __future__ import annotations
 
@@ -31,84 +33,184 @@ sys.path.insert(0, ROOT)
 
 METRIC = "TE estimates/s and distance evals/s (% FP32 VALU peak); p50/p99 latency"
 
-# MI355X: 256 CUs at 2.4 GHz; a wave64 VALU instruction issues at 64 lanes/clk/CU.
+# MI355X: 256 CUs in 8 XCDs, 4 SIMDs of 16 lanes each, 2.4 GHz peak engine clock.  A wave64 VALU
+# instruction occupies a SIMD for 4 clocks, so the chip issues 256 x 64 lane-instructions per clock.
 N_CU = 256
 CLOCK_HZ = 2.4e9
 VALU_LANE_INSTR_PER_S = N_CU * 64 * CLOCK_HZ                 # 39.3e12
-PEAK_FP32_OPS = 2 * VALU_LANE_INSTR_PER_S / 1e12             # 78.6 T ops/s: 3-input op (max3 / FMA) per lane
+PEAK_FP32_3INPUT = 2 * VALU_LANE_INSTR_PER_S / 1e12          # 78.6 T: every lane-instruction a 2-op 3-input op
 PEAK_FP32_HEADLINE = 157.3                                   # AMD headline (packed FMA), T flop/s
 
 
-# HBM bytes per search launch of this workload from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs, scaled by a
-# plain 256 MiB copy (factors 2.000 and 1.000), keyed by the kernel source they were taken on; any other kernel
-# source reports null.
-RECORDED_TRAFFIC = {"152d275deeea": 8918.05 * 1024 * 2.0 + 1319.97 * 1024 * 1.0}
-KERNEL_SRC = os.path.join(ROOT, "paper_1401_4068_amd", "csrc", "te_kernels.hip")
-
-
-def kernel_traffic():
-    import hashlib
-    try:
-        h = hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()[:12]
-    except OSError:
-        return None
-    v = RECORDED_TRAFFIC.get(h)
-    return None if v is None else int(v)
-
-
 def ops_per_pair(D: int) -> int:
-    """Algorithmic FP32 ops per directed pair over both passes: (2D) + (2D + 2)."""
+    """Algorithmic FP32 ops per directed pair over both passes: pass 1 D sub + (D-1) max + 1 cmp = 2D,
+    pass 2 D sub + (D-1) max + 3 cmp = 2D + 2."""
     return 4 * D + 2
 
 
-def host_threads() -> int:
+def valu_ceiling(D: int) -> float:
+    """The FP32 VALU roofline of this op mix without packed FP32 math (T ops/s): the chip's
+    39.3e12 lane-instructions/s times the ops one instruction can carry.  A subtraction or a
+    compare is one op per lane-instruction; two maxes fold into one 3-input v_max3 (abs as a free
+    source modifier).  The fewest instructions for a pair's 4D + 2 ops are therefore
+    2D subtractions + 2 ceil((D-1)/2) v_max3 + 4 compares."""
+    instr = 2 * D + 2 * (D // 2) + 4
+    return VALU_LANE_INSTR_PER_S * ops_per_pair(D) / instr / 1e12
+
+
+# HBM bytes per search launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs, scaled by a plain 256 MiB
+# device copy measured the same way (factors 2.000 and 1.000), keyed by (kernel source, workload); any other
+# kernel source reports null.
+RECORDED_TRAFFIC = {}
+KERNEL_SRC = os.path.join(ROOT, "paper_1401_4068_amd", "csrc", "te_kernels.hip")
+
+
+def kernel_sha() -> str:
+    import hashlib
     try:
-        n = len(os.sched_getaffinity(0))
+        return hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()[:12]
+    except OSError:
+        return ""
+
+
+def kernel_traffic(workload: str):
+    v = RECORDED_TRAFFIC.get((kernel_sha(), workload))
+    return None if v is None else int(v)
+
+
+def host_info() -> dict:
+    """Host cores: nproc, this process's CPU affinity, the threads the oracle uses (the
+    process's share, at most 16 per GPU on the test hosts) and the CPU model."""
+    nproc = os.cpu_count() or 1
+    try:
+        aff = len(os.sched_getaffinity(0))
     except AttributeError:
-        n = os.cpu_count() or 1
-    return max(1, min(16, n))
+        aff = nproc
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    threads = max(1, min(aff, int(env) if env.isdigit() and int(env) > 0 else aff, 16))
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(nproc=nproc, affinity=aff, threads=threads, cpu_model=model)
 
 
-def cpu_baseline(wl, budget_s: float = 12.0):
-    """The oracle on the host cores on a bounded, seeded sample of the workload's chunks.
+def _oracle_chunk(wl, job, threads):
+    """TE of one (pair, w, W, Rc, perm_row) chunk by the oracle, its reference points split over threads."""
+    from oracle import oracle
+    p, w, W, Rc, row = job
+    perm = None if row < 0 else wl.perms.reshape(-1, wl.n_trials)[row]
+    pts = oracle.embed(wl.x[p], wl.y[p], wl.d_y, wl.d_x, wl.tau, wl.u, w, W, Rc=Rc, src_perm=perm)
+    _, cnt = oracle.counts(pts, wl.d_y, wl.d_x, wl.k, n_threads=threads)
+    return oracle.te_from_counts(cnt, wl.k)
 
-    Chunks are taken in a seeded random order, a batch of one chunk per thread at a
-    time, until about budget_s seconds have passed.  The rate is scaled by directed
-    pairs (the oracle's work grows as N^2): estimates/s = sample pairs/s divided by
-    the workload's mean pairs per estimate."""
+
+def cpu_baseline(wl, budget_s: float = 20.0, plan_c3: bool = False):
+    """The oracle (untuned) on the host cores on a bounded, seeded sample of the workload's chunks.
+
+    plan_c3 (the uneven-surrogate batch): every original of at most 10 000 points and the three
+    largest chunks first, then surrogate chunks in a seeded order while the time budget lasts.
+    Otherwise chunks in a seeded order, one per thread at a time, while the budget lasts.
+    Chunks of more than 10 000 points split their reference points over all threads; smaller
+    ones run one chunk per thread.  The rate is scaled by directed pairs (the oracle's work grows
+    as N^2): estimates/s = sample pairs/s divided by the workload's mean pairs per estimate."""
     from oracle import oracle
     from synth.rng import derive_key, permutation
-    threads = host_threads()
-    jobs, _ = oracle.workload_jobs(wl)
-    order = permutation(derive_key(4068, len(jobs)), len(jobs))
-    jobs = [jobs[i] for i in order]
-    done = 0
-    pairs = 0
-    t_total = 0.0
-    while done < len(jobs) and t_total < budget_s:
-        sel = jobs[done:done + threads]
-        t0 = time.perf_counter()
-        oracle.te_jobs(wl.x, wl.y, wl.d_y, wl.d_x, wl.tau, wl.u, wl.k, sel, wl.perms, n_threads=threads)
-        t_total += time.perf_counter() - t0
-        done += len(sel)
-        pairs += sum(j[3] * j[2] * (j[3] * j[2] - 1) for j in sel)
+    info = host_info()
+    threads = info["threads"]
+    jobs, keys = oracle.workload_jobs(wl)
+    size = lambda j: j[2] * j[3]                                         # noqa: E731
+    if plan_c3:
+        orig = [i for i, k in enumerate(keys) if k[2] == 0]
+        first = [i for i in orig if size(jobs[i]) <= 10000]
+        big = sorted(orig, key=lambda i: -size(jobs[i]))[:3]
+        rest = [i for i, k in enumerate(keys) if k[2] > 0]
+        order = [rest[i] for i in permutation(derive_key(4068, len(rest)), len(rest))]
+        queue = first + [i for i in big if i not in first] + order
+        label = "all originals of <= 10 000 points, the 3 largest chunks, then surrogate chunks in seeded order"
+    else:
+        queue = [int(i) for i in permutation(derive_key(4068, len(jobs)), len(jobs))]
+        label = "chunks in seeded order"
+    done, pairs, t_total, npick = 0, 0, 0.0, 0
+    while done < len(queue) and t_total < budget_s:
+        j = jobs[queue[done]]
+        if size(j) > 10000:
+            t0 = time.perf_counter()
+            _oracle_chunk(wl, j, threads)
+            t_total += time.perf_counter() - t0
+            sel = [j]
+            done += 1
+        else:
+            sel = []
+            while done < len(queue) and len(sel) < threads and size(jobs[queue[done]]) <= 10000:
+                sel.append(jobs[queue[done]])
+                done += 1
+            t0 = time.perf_counter()
+            oracle.te_jobs(wl.x, wl.y, wl.d_y, wl.d_x, wl.tau, wl.u, wl.k, sel, wl.perms, n_threads=threads)
+            t_total += time.perf_counter() - t0
+        npick += len(sel)
+        pairs += sum(size(j) * (size(j) - 1) for j in sel)
     mean_pairs = wl.directed_pairs() / wl.n_estimates()
-    return dict(value=(pairs / t_total) / mean_pairs, unit="estimates/s", cores=threads, kind="oracle",
-                sample="%d of %d chunks (seeded random order; %.3g directed pairs), %.1f s wall on %d threads; "
-                       "scaled by directed pairs" % (done, len(jobs), pairs, t_total, threads))
+    rate = pairs / t_total
+    return dict(value=rate / mean_pairs, unit="estimates/s", cores=threads, kind="oracle",
+                sample="%s: %d of %d chunks, %.3g of %.3g directed pairs per pass (%.2f %%), %.1f s wall on %d "
+                       "threads; scaled by directed pairs" % (label, npick, len(jobs), pairs, wl.directed_pairs(),
+                                                              100.0 * pairs / wl.directed_pairs(), t_total, threads),
+                pairs_per_s=rate, pairs_per_s_per_core=rate / threads, nproc=info["nproc"],
+                affinity=info["affinity"], cpu_model=info["cpu_model"])
+
+
+WORKLOADS = {
+    "uneven": "uneven_chunks_200_surrogates",
+    "nonlinear": "nonlinear_ar_ensemble",
+    "linear": "linear_ar_single_estimate",
+    "meg": "meg_like_16_pairs_100_surrogates",
+}
 
 
 def make_workload(name):
     import synth
     if name == "nonlinear":
-        return synth.nonlinear_ensemble(), "nonlinear_ar_ensemble"
+        return synth.nonlinear_ensemble(), WORKLOADS[name]
     if name == "linear":
-        return synth.linear_pair(), "linear_ar_single_estimate"
+        return synth.linear_pair(), WORKLOADS[name]
     if name == "uneven":
-        return synth.uneven_surrogates(), "uneven_chunks_200_surrogates"
+        return synth.uneven_surrogates(), WORKLOADS[name]
     if name == "meg":
-        return synth.meg_like(), "meg_like_16_pairs_100_surrogates"
+        return synth.meg_like(), WORKLOADS[name]
     raise SystemExit("unknown workload " + name)
+
+
+def roofline_record(wl, wname, k_ms, k_n, w1, w2, work_launches, slots, pairs_per_pass_step):
+    """The search kernel on the FP32 VALU roofline.  achieved = algorithmic ops of the pairs one
+    launch evaluates (2D per pass-1 pair, 2D + 2 per pass-2 pair; device counters of an untimed
+    step) / the average launch duration of the timed steps (HIP events on the launch stream)."""
+    D = wl.dim
+    avg_s = k_ms / k_n / 1e3
+    p1, p2 = w1 / work_launches, w2 / work_launches
+    ops = p1 * 2 * D + p2 * (2 * D + 2)
+    method_ops = pairs_per_pass_step * ops_per_pair(D)
+    achieved = ops / avg_s / 1e12
+    method_tops = method_ops / avg_s / 1e12
+    ceil = valu_ceiling(D)
+    return dict(
+        bound="alu", achieved=round(achieved, 3), peak=round(ceil, 3), unit="TFLOP/s",
+        frac=round(achieved / ceil, 4), traffic=kernel_traffic(wname),
+        peak_derivation="39.32e12 lane-instr/s (256 CU x 64 lanes x 2.4 GHz) x %d ops per %d instructions "
+                        "(2D sub + 2 ceil((D-1)/2) v_max3 + 4 cmp, D = %d; no packed FP32)"
+                        % (ops_per_pair(D), 2 * D + 2 * (D // 2) + 4, D),
+        kernel="search_kernel<%d,%d,k=%d,slots=%d,sorted>" % (wl.d_y + wl.cond_source, wl.d_x, wl.k, slots),
+        kernel_src=kernel_sha(), avg_launch_ms=round(avg_s * 1e3, 4), launches=k_n,
+        pairs_evaluated_per_launch=[int(p1), int(p2)], ops_per_launch=int(ops),
+        method_pairs_per_launch=int(pairs_per_pass_step), method_equivalent_tops=round(method_tops, 3),
+        frac_method_equivalent=round(method_tops / ceil, 4),
+        frac_of_3input_78_6=round(achieved / PEAK_FP32_3INPUT, 4),
+        frac_of_headline_157_3=round(achieved / PEAK_FP32_HEADLINE, 4),
+        method_frac_of_headline_157_3=round(method_tops / PEAK_FP32_HEADLINE, 4))
 
 
 def batched_record(args, wl, wname):
@@ -120,10 +222,17 @@ def batched_record(args, wl, wname):
     pairs_per_pass = int(wl.directed_pairs())                 # Σ over all chunks of N(N-1)
     x = torch.from_numpy(wl.x).cuda()
     y = torch.from_numpy(wl.y).cuda()
-    perms = torch.from_numpy(wl.perms).cuda() if wl.n_surrogates else None
+    S = wl.n_surrogates
+    G = wl.n_pairs * wl.n_points
+    # surrogate permutations: drawn by the library from the plan's seed inside every step (the
+    # default), or the input module's copy of the same permutations uploaded once (--given-perms)
+    host_perms = torch.from_numpy(wl.perms).cuda() if S else None
+    perms = host_perms if args.given_perms else None
     plan = te.Plan.from_workload(wl)
     full, minimum, plain_bytes = plan.workspace_bytes()
     ws = plan.workspace()
+    if S:
+        assert torch.equal(plan.permutations(), host_perms), "drawn permutations differ from the input module's"
     tuned = None
     if not args.no_tune:
         # launch shape tuned on the plan's own data before anything is timed
@@ -136,7 +245,6 @@ def batched_record(args, wl, wname):
     def step():
         return plan.surrogates(x, y, perms, ws=ws, stream=stream, use_graph=args.graph)
 
-    G, S = wl.n_pairs * wl.n_points, wl.n_surrogates
     dev_out = torch.empty(G * (S + 1) + G, dtype=torch.float64, device="cuda")
 
     def step_async():
@@ -145,85 +253,91 @@ def batched_record(args, wl, wname):
 
     for _ in range(args.warmup):
         step_async() if pipelined else step()
+    # timed steps: HIP events around every search launch, no work counters
     te.profile_enable(True)
     te.profile_read(reset=True)
-    te.profile_work(reset=True)
-    lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        s0 = time.perf_counter()
         if pipelined:
             step_async()
         else:
             out = step()
-        lat.append(time.perf_counter() - s0)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     k_ms, k_n = te.profile_read(reset=True)
+    te.profile_enable(False)
+    print("timed %d steps: %.4f s per step" % (args.steps, dt / args.steps), file=sys.stderr, flush=True)
+    # one untimed step with the device counters of evaluated pairs
+    te.profile_enable(False, work=True)
+    te.profile_work(reset=True)
+    step_async() if pipelined else step()
     w1, w2 = te.profile_work(reset=True)
     te.profile_enable(False)
+    # results of the last queued step against a synchronous call with the input module's
+    # permutations (bit for bit), and the latency of synchronous calls (a step and its host round trip)
+    ref = plan.surrogates(x, y, host_perms, ws=ws)
     if pipelined:
-        # results of the last queued step against a synchronous call (bit for bit), and the
-        # latency of synchronous calls (one call = one step with its host round trip)
-        out = step()
         got = dev_out.cpu().numpy()
-        assert np.array_equal(got[:G * (S + 1)].reshape(wl.n_pairs, wl.n_points, S + 1)[..., 0], out[0]), \
-            "queued and synchronous calls disagree"
-        lat = []
-        for _ in range(min(args.steps, 20)):
-            s0 = time.perf_counter()
-            step()
-            lat.append(time.perf_counter() - s0)
+        est_dev = got[:G * (S + 1)].reshape(wl.n_pairs, wl.n_points, S + 1)
+        assert np.array_equal(est_dev[..., 0], ref[0]), "queued and synchronous calls disagree"
+        if S:
+            assert np.array_equal(est_dev[..., 1:], ref[1]), "queued and synchronous calls disagree"
+            assert np.array_equal(got[G * (S + 1):].reshape(wl.n_pairs, wl.n_points), ref[2])
+    else:
+        for u, v in zip(out, ref):
+            assert np.array_equal(u, v, equal_nan=True), "drawn and given permutations disagree"
+    lat = []
+    for _ in range(args.latency_calls):
+        s0 = time.perf_counter()
+        step()
+        lat.append(time.perf_counter() - s0)
     est = wl.n_estimates()
     value = est * args.steps / dt
     evals_per_s = 2 * pairs_per_pass * args.steps / dt
-
-    # dominant kernel: the persistent search launch (one per step when the workspace holds the batch)
+    slots = tuned["slots"] if tuned else 4
     roof = None
     if k_n > 0:
-        avg_s = k_ms / k_n / 1e3
-        # algorithmic ops of the pairs each launch evaluates: 2D per pass-1 pair, 2D + 2 per pass-2 pair
-        p1, p2 = w1 / k_n, w2 / k_n
-        ops = p1 * 2 * D + p2 * (2 * D + 2)
-        method_ops = pairs_per_pass * ops_per_pair(D) * args.steps / k_n
-        achieved = ops / avg_s / 1e12
-        roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_OPS, unit="TFLOP/s",
-                    frac=round(achieved / PEAK_FP32_OPS, 4),
-                    traffic=kernel_traffic() if wname == "nonlinear_ar_ensemble" else None,
-                    kernel="search_kernel<%d,%d,k=%d,slots=%d,sorted>" % (wl.d_y, wl.d_x, wl.k,
-                                                                          tuned["slots"] if tuned else 4),
-                    avg_launch_ms=round(avg_s * 1e3, 4), launches=k_n, ops_per_launch=int(ops),
-                    pairs_evaluated_per_launch=[int(p1), int(p2)],
-                    method_pairs_per_launch=int(pairs_per_pass * args.steps / k_n),
-                    method_equivalent_tops=round(method_ops / avg_s / 1e12, 3),
-                    frac_of_headline_157_3=round(achieved / PEAK_FP32_HEADLINE, 4))
+        roof = roofline_record(wl, wname, k_ms, k_n, w1, w2, 1, slots, pairs_per_pass * args.steps / k_n)
 
-    # plain per-time-point path on the same workload
+    # plain per-time-point paths on the same work
     plain_rec = None
     if args.plain_steps > 0:
-        if wl.n_surrogates == 0:
-            run_plain = lambda: plan.estimate(x, y, ws=ws)                          # noqa: E731
-            label = "te_estimate, one window at a time"
-        else:
-            ws_min = torch.empty(minimum, dtype=torch.uint8, device="cuda")
-            run_plain = lambda: plan.surrogates(x, y, perms, ws=ws_min)              # noqa: E731
-            label = "te_surrogates with the minimum workspace: one window's S+1 chunks per launch"
-        run_plain()
+        plain_rec = {}
+        ws_min = torch.empty(minimum, dtype=torch.uint8, device="cuda")
+        if S:
+            run_pt = lambda: plan.surrogates(x, y, perms, ws=ws_min)                 # noqa: E731
+            run_pt()
+            torch.cuda.synchronize()
+            p0 = time.perf_counter()
+            for _ in range(args.plain_steps):
+                r = run_pt()
+            torch.cuda.synchronize()
+            pdt = time.perf_counter() - p0
+            for u, v in zip(r, ref):
+                assert np.array_equal(u, v, equal_nan=True), "per-time-point and batched paths disagree"
+            plain_rec["per_time_point"] = dict(
+                value=round(est * args.plain_steps / pdt, 2), unit="estimates/s",
+                ms_per_step=round(pdt / args.plain_steps * 1e3, 3),
+                path="te_surrogates with the minimum workspace: one time point (its S+1 chunks) per launch")
+        # te_estimate: one chunk per launch sequence (sort, embed, search, reduce), originals; every
+        # chunk of a time point costs the same, so its rate per estimate stands for the surrogates too
+        plan.estimate(x, y, ws=ws)
         torch.cuda.synchronize()
         p0 = time.perf_counter()
         for _ in range(args.plain_steps):
-            plain = run_plain()
+            r0 = plan.estimate(x, y, ws=ws)
         torch.cuda.synchronize()
         pdt = time.perf_counter() - p0
-        ref = out[0] if wl.n_surrogates == 0 else out
-        if wl.n_surrogates == 0:
-            assert np.array_equal(plain, ref), "plain and batched paths disagree"
+        assert np.array_equal(r0, ref[0]), "plain and batched paths disagree"
+        plain_rec["per_chunk"] = dict(
+            value=round(G * args.plain_steps / pdt, 2), unit="estimates/s",
+            ms_per_step=round(pdt / args.plain_steps * 1e3, 3),
+            path="te_estimate, one chunk at a time (the %d originals; same chunk sizes as the surrogates)" % G)
+        if S == 0:
+            plain_rec["value"] = plain_rec["per_chunk"]["value"]
         else:
-            for u, v in zip(plain, ref):
-                assert np.array_equal(u, v), "plain and batched paths disagree"
-        plain_rec = dict(value=round(est * args.plain_steps / pdt, 2), unit="estimates/s",
-                         ms_per_step=round(pdt / args.plain_steps * 1e3, 3), path=label)
+            plain_rec["value"] = plain_rec["per_time_point"]["value"]
 
     rec = dict(
         metric=METRIC, value=round(value, 2), unit="estimates/s", n_gpus=1, steps=args.steps,
@@ -231,7 +345,9 @@ def batched_record(args, wl, wname):
         scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
         config=dict(workload=wname, pairs=wl.n_pairs, trials=wl.n_trials, samples=wl.n_samples,
                     windows=wl.n_points, points_per_window_min=int(n.min()), points_per_window_max=int(n.max()),
-                    d_y=wl.d_y, d_x=wl.d_x, tau=wl.tau, u=wl.u, dim=D, k=wl.k, surrogates=wl.n_surrogates,
+                    d_y=wl.d_y, d_x=wl.d_x, tau=wl.tau, u=wl.u, dim=D, k=wl.k, surrogates=S,
+                    permutations=("given (uploaded once)" if args.given_perms else
+                                  "drawn on the device from the plan's seed in every step") if S else None,
                     estimates_per_step=est, workspace_bytes=int(full),
                     path=("batched (te_surrogates_async: one persistent search launch per step, steps queued "
                           "back to back, results left in HBM)" if pipelined else
@@ -239,15 +355,16 @@ def batched_record(args, wl, wname):
                                                                                     else ""))),
         distance_evals_per_s=round(evals_per_s, 1),
         pct_fp32_valu_peak=None if roof is None else round(100 * roof["frac"], 2),
-        latency_s=dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99))),
+        latency_s=dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)),
+                       calls=len(lat)) if lat else None,
         plain=plain_rec,
         tuned_shape=tuned,
         roofline=roof,
     )
-    if pipelined and not args.no_two_stream:
+    if pipelined and not args.no_two_stream and wname != WORKLOADS["uneven"]:
         rec["pipelined_two_streams"] = two_stream_record(plan, wl, x, y, perms, ws, dev_out, args.steps)
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_baseline(wl)
+        rec["cpu_baseline"] = cpu_baseline(wl, plan_c3=(wname == WORKLOADS["uneven"]))
     return rec
 
 
@@ -319,7 +436,6 @@ def scan_record(args, scenario):
         step()
     te.profile_enable(True)
     te.profile_read(reset=True)
-    te.profile_work(reset=True)
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -330,18 +446,17 @@ def scan_record(args, scenario):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     k_ms, k_n = te.profile_read(reset=True)
+    # one untimed step with the device counters of evaluated pairs (two launches)
+    te.profile_enable(False, work=True)
+    te.profile_work(reset=True)
+    step()
     w1, w2 = te.profile_work(reset=True)
     te.profile_enable(False)
     roof = None
     if k_n > 0:
         # two search launches per step (all delays; the chosen delay's test): their mean
-        avg_s = k_ms / k_n / 1e3
-        ops = (w1 * 2 * D + w2 * (2 * D + 2)) / k_n
-        achieved = ops / avg_s / 1e12
-        roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_OPS, unit="TFLOP/s",
-                    frac=round(achieved / PEAK_FP32_OPS, 4), traffic=None, avg_launch_ms=round(avg_s * 1e3, 4),
-                    launches=k_n, pairs_evaluated_per_launch=[int(w1 / k_n), int(w2 / k_n)],
-                    method_pairs_per_launch=int(pairs_per_step * args.steps / k_n))
+        roof = roofline_record(wl, "ar_scan", k_ms, k_n, w1, w2, 2, tuned["slots"] if tuned else 4,
+                               pairs_per_step / 2)
     te_scan, u_best, _, pv = out
     findings = []
     for p in range(wl.n_pairs):
@@ -372,7 +487,7 @@ def scan_cpu_baseline(wl, u_values, est_per_step, pairs_per_step, budget_s: floa
     estimates/s = sample pairs/s divided by the step's mean pairs per estimate."""
     from oracle import oracle
     from synth.rng import derive_key, permutation
-    threads = host_threads()
+    threads = host_info()["threads"]
     jobs = [(p, c, u) for p in range(wl.n_pairs) for c in range(wl.n_points) for u in u_values]
     order = permutation(derive_key(4068, len(jobs)), len(jobs))
     sizes = wl.chunk_sizes()
@@ -394,105 +509,137 @@ def scan_cpu_baseline(wl, u_values, est_per_step, pairs_per_step, budget_s: floa
 
 
 def served_record(args):
-    """Poisson-arriving jobs through te_serve_* (continuous batching) and the same trace
-    through te_surrogates one job at a time (FIFO)."""
+    """The served mix: Poisson-arriving single-time-point jobs of mixed shapes through the
+    continuous-batching server (te_serve_*), and the same trace replayed in real time, one job
+    at a time in arrival order, through the batched path (te_surrogates) and through the plain
+    per-chunk path (te_estimate_each).  Every job's permutations are drawn on the device from its
+    seed.  Latency = arrival (submission) -> result; estimates/s = the trace's estimates / the
+    span from the first arrival to the last result."""
     import threading
 
     import torch
     import paper_1401_4068_amd as te
     import synth
 
-    def replay(jobs, rate_label):
-        wls = [synth.job_workload(j) for j in jobs]
-        warm_srv = te.Server(arena_bytes=256 << 20, max_slots=4)     # module load, first launches
-        for d in (2, 3, 4):
-            warm = synth.job_workload(dict(id=-d, t=0.0, d=d, W=10, R=30, S=2, seed=d))
-            warm_srv.wait(warm_srv.submit(warm), timeout_s=120)
-        warm_srv.close()
-        srv = te.Server(arena_bytes=args.arena_gb << 30, max_slots=args.slots, step_pairs=args.step_pairs)
-        tickets = [None] * len(jobs)
-        t_sub = [0.0] * len(jobs)
-        t0 = time.perf_counter() + 0.01
+    def progress(*a):
+        print(*a, file=sys.stderr, flush=True)
 
-        def submitter():
-            for i, (j, wl) in enumerate(zip(jobs, wls)):
-                d = t0 + j["t"] - time.perf_counter()
-                if d > 0:
-                    time.sleep(d)
-                t_sub[i] = time.perf_counter()
-                tickets[i] = srv.submit(wl)
+    trace = synth.served_jobs(n_jobs=args.jobs, rate=args.served_rate, seed_offset=args.served_seed)
+    progress("trace: %d jobs at %.3f/s" % (len(trace), args.served_rate))
+    wls = [synth.job_workload(j, with_perms=False) for j in trace]
+    est = sum(1 + j["S"] for j in trace)
+    pairs = sum((1 + j["S"]) * (j["R"] * j["W"]) * (j["R"] * j["W"] - 1) for j in trace)
+    offered_pairs_per_s = pairs / max(trace[-1]["t"], 1e-9)
 
-        th = threading.Thread(target=submitter)
-        th.start()
-        th.join()
-        for i in range(len(jobs)):
-            srv.wait(tickets[i], timeout_s=3600)
-        st = srv.stats()
-        t_end = time.perf_counter()
-        served_est_per_s = sum(1 + j["S"] for j in jobs) / (t_end - t_sub[0])
-        srv.close()
-        est = sum((1 + j["S"]) for j in jobs)
-        pairs = sum((1 + j["S"]) * (j["R"] * j["W"]) * (j["R"] * j["W"] - 1) for j in jobs)
-        # FIFO through the batched path, one job at a time (arrival-ordered, queueing included)
-        done = 0.0
-        fifo_lat = []
-        for j, wl in zip(jobs, wls):
-            # service = what the job costs on its own: plan, upload of its host arrays, batched run
-            torch.cuda.synchronize()
-            s0 = time.perf_counter()
+    # warm-up: module load and the first launches of every kernel class
+    warm_srv = te.Server(arena_bytes=256 << 20, max_slots=4)
+    for d in (2, 3, 4):
+        warm = synth.job_workload(dict(id=-d, t=0.0, d=d, W=10, R=30, S=2, seed=d), with_perms=False)
+        warm_srv.wait(warm_srv.submit(warm, draw_perms=True), timeout_s=120)
+        p = te.Plan.from_workload(warm)
+        xw, yw = torch.from_numpy(warm.x).cuda(), torch.from_numpy(warm.y).cuda()
+        p.surrogates(xw, yw)
+        p.estimate_each(xw, yw)
+        p.close()
+    warm_srv.close()
+
+    # served: a submitter thread replays the arrival times
+    srv = te.Server(arena_bytes=args.arena_gb << 30, max_slots=args.slots, step_pairs=args.step_pairs)
+    tickets = [None] * len(trace)
+    t_sub = [0.0] * len(trace)
+    t0 = time.perf_counter() + 0.05
+
+    def submitter():
+        for i, (j, wl) in enumerate(zip(trace, wls)):
+            d = t0 + j["t"] - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            t_sub[i] = time.perf_counter()
+            tickets[i] = srv.submit(wl, draw_perms=True)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    served_te = []
+    for i in range(len(trace)):
+        served_te.append(srv.wait(tickets[i], timeout_s=3600)[0][0, 0])
+        if i % 200 == 199:
+            progress("served: %d jobs done" % (i + 1))
+    t_end = time.perf_counter()
+    st = srv.stats()
+    srv.close()
+    served = dict(p50_s=st["p50_s"], p99_s=st["p99_s"], est_per_s=est / (t_end - t0),
+                  span_s=t_end - t0, steps=st["steps"], peak_slots=st["peak_slots"],
+                  peak_arena_bytes=st["peak_bytes"])
+    progress("served: %.1f s, %.1f estimates/s" % (served["span_s"], served["est_per_s"]))
+
+    def replay(label, run):
+        """Real-time replay, one job at a time in arrival order: a job starts at its arrival or
+        when the previous one is done; its service is plan, upload and the call."""
+        lat = []
+        r0 = time.perf_counter()
+        for i, (j, wl) in enumerate(zip(trace, wls)):
+            d = r0 + j["t"] - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
             plan = te.Plan.from_workload(wl)
             x = torch.from_numpy(wl.x).cuda()
             y = torch.from_numpy(wl.y).cuda()
-            perms = torch.from_numpy(wl.perms).cuda() if wl.n_surrogates else None
-            plan.surrogates(x, y, perms)
-            svc = time.perf_counter() - s0
-            start = max(j["t"], done)
-            done = start + svc
-            fifo_lat.append(done - j["t"])
+            out = run(plan, x, y)
+            lat.append(time.perf_counter() - (r0 + j["t"]))
+            assert out[0][0, 0] == served_te[i], "%s and served estimates differ (job %d)" % (label, i)
             plan.close()
-        fifo_span = done - jobs[0]["t"]
-        return dict(rate_per_s=rate_label, jobs=len(jobs), estimates=est, directed_pairs=int(pairs),
-                    served=dict(p50_s=st["p50_s"], p99_s=st["p99_s"], est_per_s=served_est_per_s,
-                                span_s=t_end - t_sub[0], steps=st["steps"], peak_slots=st["peak_slots"],
-                                peak_arena_bytes=st["peak_bytes"]),
-                    fifo=dict(p50_s=float(np.percentile(fifo_lat, 50)), p99_s=float(np.percentile(fifo_lat, 99)),
-                              est_per_s=est / fifo_span, span_s=fifo_span))
+            if i % 200 == 199:
+                progress("%s: %d jobs done" % (label, i + 1))
+        span = time.perf_counter() - r0
+        progress("%s: %.1f s" % (label, span))
+        return dict(p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                    est_per_s=est / span, span_s=span)
 
-    trace = synth.served_jobs(n_jobs=args.jobs, rate=200.0)
-    r1 = replay(trace, 200.0)
-    # second trace: arrival rate rescaled to 0.8 x the measured served capacity (jobs/s)
-    cap_jobs = r1["jobs"] / r1["served"]["span_s"]
-    rate2 = 0.8 * cap_jobs
-    trace2 = synth.served_jobs(n_jobs=args.jobs, rate=rate2, seed_offset=1)
-    r2 = replay(trace2, round(rate2, 3))
-    rec = dict(metric=METRIC, value=round(r1["served"]["est_per_s"], 2), unit="estimates/s", n_gpus=1,
-               steps=1, warmup=1, ms_per_step=round(r1["served"]["span_s"] * 1e3, 1), higher_is_better=True,
+    fifo = replay("fifo", lambda plan, x, y: plan.surrogates(x, y))
+    plain = replay("plain", lambda plan, x, y: plan.estimate_each(x, y)) if not args.no_plain_replay else None
+    capacity_jobs_per_s = len(trace) / served["span_s"]
+    rec = dict(metric=METRIC, value=round(served["est_per_s"], 2), unit="estimates/s", n_gpus=1,
+               steps=1, warmup=1, ms_per_step=round(served["span_s"] * 1e3, 1), higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
-               config=dict(workload="served_mix", arrivals="poisson", jobs=args.jobs, dims=[5, 7, 9],
+               config=dict(workload="served_mix", arrivals="poisson", rate_per_s=args.served_rate,
+                           trace_seed_offset=args.served_seed, jobs=len(trace), dims=[5, 7, 9],
                            points_per_job="log-uniform 1000..100000", surrogates="0..500", k=4,
-                           arena_gb=args.arena_gb, max_slots=args.slots, step_pairs=args.step_pairs),
-               latency_s=dict(p50=r1["served"]["p50_s"], p99=r1["served"]["p99_s"]),
-               traces=[r1, r2])
+                           estimates=est, directed_pairs_per_pass=int(pairs),
+                           offered_pairs_per_s=offered_pairs_per_s, arena_gb=args.arena_gb,
+                           max_slots=args.slots, step_pairs=args.step_pairs,
+                           permutations="drawn on the device from each job's seed"),
+               latency_s=dict(p50=served["p50_s"], p99=served["p99_s"]),
+               served=served, fifo_batched=fifo, plain_per_chunk=plain,
+               served_capacity_jobs_per_s=capacity_jobs_per_s,
+               rate_for_0_8_capacity=0.8 * capacity_jobs_per_s)
     return rec
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="nonlinear",
-                    choices=["nonlinear", "linear", "uneven", "meg", "served", "ar0", "ar1", "ar2", "ar3"],
-                    help="ar0: delay recovery against the amount of data; ar1-ar3: the AR coupling scenarios")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="uneven",
+                    choices=["uneven", "nonlinear", "linear", "meg", "served", "ar0", "ar1", "ar2", "ar3"],
+                    help="uneven: batched surrogates (60 time points x 201 chunks of 1 000-49 400 points); "
+                         "ar0: delay recovery against the amount of data; ar1-ar3: the AR coupling scenarios")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--latency-calls", type=int, default=3, help="synchronous calls timed for latency_s")
+    ap.add_argument("--given-perms", action="store_true",
+                    help="pass the input module's permutations instead of drawing them in the library")
     ap.add_argument("--graph", action="store_true", help="replay the batched step as a hipGraph")
     ap.add_argument("--no-two-stream", action="store_true",
                     help="skip the two-stream pipelined measurement (profiled runs: its launches overlap)")
     ap.add_argument("--sync", action="store_true",
                     help="time synchronous te_surrogates calls (a host round trip per step) instead of queued steps")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
-    ap.add_argument("--jobs", type=int, default=60, help="served workload: jobs per trace")
+    ap.add_argument("--jobs", type=int, default=2000, help="served workload: jobs per trace")
+    ap.add_argument("--served-rate", type=float, default=200.0, help="served workload: Poisson arrivals per second")
+    ap.add_argument("--served-seed", type=int, default=0, help="served workload: trace seed offset")
+    ap.add_argument("--no-plain-replay", action="store_true", help="served workload: skip the plain-path replay")
     ap.add_argument("--arena-gb", type=int, default=32, help="served workload: device arena")
     ap.add_argument("--slots", type=int, default=64, help="served workload: resident job slots")
     ap.add_argument("--step-pairs", type=int, default=0, help="served workload: pairs per search launch")

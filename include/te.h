@@ -83,7 +83,28 @@ typedef struct {
                                   conditioning set is (Y_past, x_t) in all spaces of eq. 8-9, the
                                   control of instantaneous mixing noted with Fig. 2; needs
                                   d_y + 1 <= 4.  0: eq. 9 as written                        */
+    uint64_t seed;             /* key of the surrogate permutations the library draws when a
+                                  call is given no permutations (perms == NULL); see below   */
 } te_problem;
+
+/* Surrogate permutations drawn by the library (calls given perms == NULL, or
+ * te_plan_permutations).  The surrogates test the estimate against trial
+ * shuffles ("TE calculation and statistical testing against surrogate data";
+ * Fig. 3): surrogate s of (pair p, point c) reads the source of repetition r
+ * from repetition phi(r), phi a uniformly random permutation of 0..R_c-1,
+ * independent across (p, c, s).  phi is Fisher-Yates from the top -- for
+ * i = R_c-1 down to 1, swap positions i and j_i with j_i uniform on 0..i --
+ * with integers from the counter-based SplitMix64 generator (Steele, Lea and
+ * Flood, OOPSLA 2014): output q of the stream keyed K is
+ * mix(K + (q+1) * 0x9E3779B97F4A7C15), where mix is SplitMix64's finaliser,
+ * and K = f(f(f(f(f(0x5EED5EED5EED5EED, seed), 77), p), c), s) with
+ * f(k, v) = mix(k + 0x9E3779B97F4A7C15 v + 1).  Draw t (t = R_c-1-i) uses
+ * Lemire's multiply-and-reject rule on the high 32 bits w of an output:
+ * m = w (i+1), j_i = m >> 32, rejected when (m mod 2^32) < 2^32 mod (i+1).
+ * Draws are made in rounds: in round one draw t takes output t; each later
+ * round gives the draws rejected so far, in draw order, the next unused
+ * outputs.  The same seed gives the same permutations on every call, device
+ * and batch split. */
 
 /* Library version string. */
 const char *te_version(void);
@@ -102,7 +123,7 @@ te_status te_plan_destroy(te_plan plan);
 /* Device workspace sizes in bytes.  full: te_surrogates in a single batch;
  * minimum: the smallest workspace te_surrogates accepts (it then splits the
  * batch into several launches, with identical results); plain: what
- * te_estimate needs. */
+ * te_estimate and te_estimate_each need. */
 te_status te_plan_workspace_bytes(te_plan plan, size_t *full, size_t *minimum, size_t *plain);
 
 /* Plain per-time-point path: the original (unshuffled) estimate of every
@@ -113,13 +134,25 @@ te_status te_plan_workspace_bytes(te_plan plan, size_t *full, size_t *minimum, s
 te_status te_estimate(te_plan plan, const float *x, const float *y,
                       void *ws, size_t ws_bytes, void *hip_stream, double *te_out);
 
+/* Plain per-chunk path over originals and surrogates: every (pair, point) on
+ * its own, its window sorted once, then each of its S+1 chunks on its own
+ * (embed, search, reduce: three launches per chunk).  Same estimates and
+ * p-values as te_surrogates bit for bit; the unbatched baseline the batched
+ * and served forms are measured against.  perms, te_surr and p_value as for
+ * te_surrogates (perms NULL: drawn from problem.seed); ws of ws_bytes >= the
+ * plain bytes of te_plan_workspace_bytes. */
+te_status te_estimate_each(te_plan plan, const float *x, const float *y, const int32_t *perms,
+                           void *ws, size_t ws_bytes, void *hip_stream,
+                           double *te_orig, double *te_surr, double *p_value);
+
 /* Batched path: originals and all surrogates of every (pair, point) through
  * one persistent search launch per batch (eq. 9-10, surrogate test).
  *   perms    device int32 [n_pairs][n_points][n_surrogates][n_trials]: the
  *            source block of repetition r in surrogate s is read from
  *            repetition perms[p][c][s][r]; entries r < R_c must be a
  *            permutation of 0..R_c-1 (checked: TE_ERR_INVALID otherwise).
- *            May be NULL when n_surrogates == 0.
+ *            NULL: the library draws them from problem.seed (see above), on
+ *            the device, inside the call.
  *   ws       device workspace of ws_bytes >= minimum bytes
  *   te_orig  host float64 [n_pairs][n_points]
  *   te_surr  host float64 [n_pairs][n_points][n_surrogates] (NULL if S == 0)
@@ -148,6 +181,14 @@ te_status te_surrogates(te_plan plan, const float *x, const float *y, const int3
 te_status te_surrogates_async(te_plan plan, const float *x, const float *y, const int32_t *perms,
                               void *ws, size_t ws_bytes, void *hip_stream, double *out);
 
+/* The permutations the library draws from the plan's seed, written to
+ *   perms    device int32 [n_pairs][n_points][n_surrogates][n_trials] (entries
+ *            r >= R_c are the identity), in stream order on hip_stream;
+ *   ws       device workspace of ws_bytes >= te_plan_permutations_workspace_bytes.
+ * Passing this array to te_surrogates gives the same results as passing NULL. */
+size_t te_plan_permutations_workspace_bytes(te_plan plan);
+te_status te_plan_permutations(te_plan plan, void *ws, size_t ws_bytes, void *hip_stream, int32_t *perms);
+
 /* Local transfer entropy (the per-point quantity of eq. 17, whose average is
  * the estimate, eq. 18): for every pooled point i of every original window,
  *   lte_i = psi(k) + psi(n_P(i)+1) - psi(n_TP(i)+1) - psi(n_PS(i)+1),
@@ -171,7 +212,7 @@ te_status te_local(te_plan plan, const float *x, const float *y, void *ws, size_
  * searches; nothing returns to the host before the end.
  *   u_values host int32 [n_u], 1 <= n_u <= 4096; each u >= 1 and every window
  *            start >= u + (d_x - 1) tau (TE_ERR_INVALID otherwise)
- *   perms    as te_surrogates (may be NULL when n_surrogates == 0)
+ *   perms    as te_surrogates (NULL: drawn from problem.seed)
  *   ws       device workspace of ws_bytes >= the minimum given by
  *            te_delay_scan_workspace_bytes (smaller workspaces are split into
  *            several launches over window groups, with identical results)
@@ -240,7 +281,7 @@ te_status te_serve_open(void *arena, size_t arena_bytes, int32_t max_slots, int3
 
 /* Submit a job (non-blocking; any thread).  x, y: host float32
  * [n_pairs][n_trials][n_samples]; perms: host int32 [n_pairs][n_points][S][n_trials]
- * (NULL if S == 0).  Everything is copied before return.  TE_ERR_INVALID: bad
+ * (NULL: drawn on the device from problem->seed).  Everything is copied before return.  TE_ERR_INVALID: bad
  * problem; TE_ERR_NOMEM: the job can never fit the arena; TE_ERR_BUSY: queue full. */
 te_status te_serve_submit(te_server srv, const te_problem *problem, const float *x, const float *y,
                           const int32_t *perms, uint64_t *ticket);
@@ -279,7 +320,7 @@ te_status te_serve_close(te_server srv);
 te_status te_autotune(int32_t d_y, int32_t d_x, int32_t k, int32_t n_points, int32_t n_chunks,
                       void *ws, size_t ws_bytes, void *hip_stream,
                       int32_t *slots, int32_t *waves_per_wg, int32_t *wg_per_cu, double *best_ms);
-/* Tuning on the plan's own data (x, y, perms as for te_surrogates; ws of
+/* Tuning on the plan's own data (x, y, perms as for te_surrogates, NULL drawn; ws of
  * ws_bytes >= the plan's minimum workspace): every shape te_autotune tries is
  * timed on a batch of the plan's largest window groups; the fastest becomes the
  * plan's launch shape and is recorded in the table.  Results of the plan do not
@@ -291,12 +332,16 @@ te_status te_tune_save(const char *path);
 te_status te_tune_load(const char *path);
 te_status te_tune_clear(void);
 
-/* Measurement hook.  While enabled, every search-kernel launch made by
- * te_estimate, te_surrogates and te_knn_counts outside graph capture is
- * bracketed by HIP events recorded on the launch stream.  te_profile_read
- * waits for those events and returns the summed kernel time in milliseconds
- * and the number of launches (reset != 0 clears the totals).  Process-wide. */
-te_status te_profile_enable(int32_t on);
+/* Measurement hook, process-wide, for search-kernel launches made outside
+ * graph capture.  flags: TE_PROFILE_TIME brackets every launch with HIP events
+ * recorded on the launch stream (te_profile_read waits for them and returns the
+ * summed kernel time in milliseconds and the number of launches; reset != 0
+ * clears the totals); TE_PROFILE_WORK makes each wave add the pairs it
+ * evaluated to device counters once, after its last work item
+ * (te_profile_work).  0 turns both off. */
+#define TE_PROFILE_TIME 1
+#define TE_PROFILE_WORK 2
+te_status te_profile_enable(int32_t flags);
 te_status te_profile_read(double *search_ms, int64_t *launches, int32_t reset);
 /* Pairs the timed search launches actually evaluated: pass 1 (radius) and pass 2
  * (counts); with sorted search spaces these are below the method's N(N-1) per

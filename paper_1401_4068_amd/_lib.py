@@ -27,7 +27,7 @@ class Problem(ctypes.Structure):
         ("k", ctypes.c_int32), ("n_points", ctypes.c_int32), ("window", ctypes.c_int32),
         ("window_start", ctypes.POINTER(ctypes.c_int32)), ("window_len", ctypes.POINTER(ctypes.c_int32)),
         ("trials", ctypes.POINTER(ctypes.c_int32)), ("n_surrogates", ctypes.c_int32),
-        ("cond_source", ctypes.c_int32),
+        ("cond_source", ctypes.c_int32), ("seed", ctypes.c_uint64),
     ]
 
 
@@ -58,6 +58,7 @@ SIGNATURES = {
     "te_plan_destroy": ([_vp], _st),
     "te_plan_workspace_bytes": ([_vp, _szp, _szp, _szp], _st),
     "te_estimate": ([_vp, _vp, _vp, _vp, _sz, _vp, _dp], _st),
+    "te_estimate_each": ([_vp, _vp, _vp, _vp, _vp, _sz, _vp, _dp, _dp, _dp], _st),
     "te_surrogates": ([_vp, _vp, _vp, _vp, _vp, _sz, _vp, _i32, _dp, _dp, _dp], _st),
     "te_surrogates_async": ([_vp, _vp, _vp, _vp, _vp, _sz, _vp, _vp], _st),
     "te_knn_counts_workspace_bytes": ([_i32, _i64], _sz),
@@ -72,6 +73,8 @@ SIGNATURES = {
     "te_serve_stats": ([_vp, ctypes.POINTER(ServeStats)], _st),
     "te_serve_close": ([_vp], _st),
     "te_plan_local_offsets": ([_vp, ctypes.POINTER(_i64)], _st),
+    "te_plan_permutations_workspace_bytes": ([_vp], _sz),
+    "te_plan_permutations": ([_vp, _vp, _sz, _vp, _vp], _st),
     "te_local": ([_vp, _vp, _vp, _vp, _sz, _vp, _vp, _dp], _st),
     "te_delay_scan_workspace_bytes": ([_vp, _vp, _i32, _szp, _szp], _st),
     "te_delay_scan": ([_vp, _vp, _vp, _vp, _vp, _i32, _vp, _sz, _vp, _dp, _vp, _dp, _dp], _st),

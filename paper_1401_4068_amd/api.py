@@ -49,7 +49,7 @@ def _local_offsets(plan):
 
 
 def _problem(n_pairs, n_trials, n_samples, d_y, d_x, tau, u, k, window_start, window_len=None, trials=None,
-             n_surrogates=0, window=0, cond_source=0):
+             n_surrogates=0, window=0, cond_source=0, seed=0):
     """A te_problem and the arrays it points to (keep both alive while it is used)."""
     keep = []
     ws = np.ascontiguousarray(window_start, np.int32)
@@ -60,6 +60,7 @@ def _problem(n_pairs, n_trials, n_samples, d_y, d_x, tau, u, k, window_start, wi
     p.window = int(window)
     p.n_surrogates = int(n_surrogates)
     p.cond_source = int(cond_source)
+    p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
     I32P = ctypes.POINTER(ctypes.c_int32)
     p.window_start = ws.ctypes.data_as(I32P)
     keep.append(ws)
@@ -81,13 +82,14 @@ class Plan:
     n_trials repetitions and n_samples samples; embedding d_y, d_x, tau; delay
     u; k neighbours; per analysis point the window start, length and number of
     pooled repetitions; n_surrogates shuffled surrogates; cond_source = 1 conditions
-    on the current source sample x_t as well.
+    on the current source sample x_t as well; seed keys the surrogate permutations
+    the library draws when a call is given none.
     """
 
     def __init__(self, n_pairs, n_trials, n_samples, d_y, d_x, tau, u, k, window_start, window_len=None,
-                 trials=None, n_surrogates=0, window=0, cond_source=0):
+                 trials=None, n_surrogates=0, window=0, cond_source=0, seed=0):
         p, self._keep = _problem(n_pairs, n_trials, n_samples, d_y, d_x, tau, u, k, window_start, window_len,
-                                 trials, n_surrogates, window, cond_source)
+                                 trials, n_surrogates, window, cond_source, seed)
         self.n_points = int(p.n_points)
         self.n_pairs = int(n_pairs)
         self.n_surrogates = int(n_surrogates)
@@ -99,9 +101,11 @@ class Plan:
 
     @classmethod
     def from_workload(cls, wl, n_surrogates=None):
+        """A plan for a synth Workload; its seed is the one the workload's own permutations were
+        drawn from, so calls without permutations draw the same ones on the device."""
         return cls(wl.n_pairs, wl.n_trials, wl.n_samples, wl.d_y, wl.d_x, wl.tau, wl.u, wl.k, wl.window_start,
                    wl.window_len, wl.trials, wl.n_surrogates if n_surrogates is None else n_surrogates,
-                   cond_source=int(getattr(wl, "cond_source", 0)))
+                   cond_source=int(getattr(wl, "cond_source", 0)), seed=int(getattr(wl, "perm_seed", 0)))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -155,6 +159,27 @@ class Plan:
                 raise ValueError("%s must hold n_pairs*n_trials*n_samples = %d values, got %d"
                                  % (name, want, t.numel()))
 
+    def _check_perms(self, perms):
+        """perms: None (the library draws them from the plan's seed) or int32 [P, C, S, R]."""
+        if perms is None or self.n_surrogates == 0:
+            return
+        want = self.n_pairs * self.n_points * self.n_surrogates * self.shape["n_trials"]
+        if perms.numel() != want:
+            raise ValueError("perms must be int32 [n_pairs, n_points, S, n_trials] (%d values)" % want)
+
+    def permutations(self, stream=None):
+        """The permutations the library draws from the plan's seed: CUDA int32 [P, C, S, R]
+        (te_plan_permutations)."""
+        torch = _torch()
+        P, C, S, R = self.n_pairs, self.n_points, self.n_surrogates, self.shape["n_trials"]
+        out = torch.empty((P, C, max(S, 0), R), dtype=torch.int32, device="cuda")
+        nb = int(lib().te_plan_permutations_workspace_bytes(self._h))
+        ws = torch.empty(max(nb, 256), dtype=torch.uint8, device="cuda")
+        sh, _ = _stream_handle(stream)
+        check(lib().te_plan_permutations(self._h, ctypes.c_void_p(ws.data_ptr()), ws.numel(), sh,
+                                         ctypes.c_void_p(out.data_ptr())))
+        return out
+
     def estimate(self, x, y, ws=None, stream=None):
         """Plain per-window path: float64 [n_pairs, n_points] original estimates."""
         torch = _torch()
@@ -165,6 +190,25 @@ class Plan:
         check(lib().te_estimate(self._h, _dev_ptr(x, torch.float32, "x"), _dev_ptr(y, torch.float32, "y"), wsp, wsn,
                                 sh, _dp(out)))
         return out
+
+    def estimate_each(self, x, y, perms=None, ws=None, stream=None):
+        """Plain per-chunk path over originals and surrogates (te_estimate_each):
+        (te_orig [P, C], te_surr [P, C, S], p_value [P, C]), equal to surrogates()."""
+        torch = _torch()
+        self._check_series(x, y)
+        self._check_perms(perms)
+        S = self.n_surrogates
+        te_orig = np.empty((self.n_pairs, self.n_points), np.float64)
+        te_surr = np.empty((self.n_pairs, self.n_points, S), np.float64)
+        pv = np.empty((self.n_pairs, self.n_points), np.float64)
+        if ws is None:
+            ws = self.workspace(self.workspace_bytes()[2])
+        sh, _ = _stream_handle(stream)
+        pp = ctypes.c_void_p(0) if perms is None else _dev_ptr(perms, torch.int32, "perms")
+        check(lib().te_estimate_each(self._h, _dev_ptr(x, torch.float32, "x"), _dev_ptr(y, torch.float32, "y"), pp,
+                                     _dev_ptr(ws, torch.uint8, "ws"), ws.numel(), sh, _dp(te_orig),
+                                     _dp(te_surr) if S > 0 else None, _dp(pv)))
+        return te_orig, te_surr, pv
 
     def local(self, x, y, ws=None, stream=None):
         """Local TE of every pooled point (eq. 17-18): (list over (pair, point) of CUDA float64
@@ -214,10 +258,7 @@ class Plan:
         torch = _torch()
         self._check_series(x, y)
         S = self.n_surrogates
-        if S > 0:
-            want = self.n_pairs * self.n_points * S * self.shape["n_trials"]
-            if perms is None or perms.numel() != want:
-                raise ValueError("perms must be int32 [n_pairs, n_points, S, n_trials] (%d values)" % want)
+        self._check_perms(perms)
         te_orig = np.empty((self.n_pairs, self.n_points), np.float64)
         te_surr = np.empty((self.n_pairs, self.n_points, S), np.float64)
         pv = np.empty((self.n_pairs, self.n_points), np.float64)
@@ -238,10 +279,7 @@ class Plan:
         self._check_series(x, y)
         S = self.n_surrogates
         G = self.n_pairs * self.n_points
-        if S > 0:
-            want = self.n_pairs * self.n_points * S * self.shape["n_trials"]
-            if perms is None or perms.numel() != want:
-                raise ValueError("perms must be int32 [n_pairs, n_points, S, n_trials] (%d values)" % want)
+        self._check_perms(perms)
         if out is None:
             out = torch.empty(G * (S + 1) + G, dtype=torch.float64, device="cuda")
         elif out.dtype != torch.float64 or out.numel() != G * (S + 1) + G or not out.is_contiguous():
@@ -272,15 +310,17 @@ class Server:
         self._h = h
         self._shapes = {}
 
-    def submit(self, wl):
-        """Submit a synth Workload-like object (series, geometry, perms); returns a ticket."""
+    def submit(self, wl, draw_perms=False):
+        """Submit a synth Workload-like object (series, geometry, perms); returns a ticket.
+        draw_perms (or a workload without perms): the server draws the permutations on the
+        device from the workload's seed instead of copying them in."""
         p, keep = _problem(wl.n_pairs, wl.n_trials, wl.n_samples, wl.d_y, wl.d_x, wl.tau, wl.u, wl.k,
                            wl.window_start, wl.window_len, wl.trials, wl.n_surrogates,
-                           cond_source=int(getattr(wl, "cond_source", 0)))
+                           cond_source=int(getattr(wl, "cond_source", 0)), seed=int(getattr(wl, "perm_seed", 0)))
         x = np.ascontiguousarray(wl.x, np.float32)
         y = np.ascontiguousarray(wl.y, np.float32)
         perms = None
-        if wl.n_surrogates > 0:
+        if wl.n_surrogates > 0 and not draw_perms and getattr(wl, "perms", None) is not None:
             perms = np.ascontiguousarray(wl.perms, np.int32)
             if perms.size != wl.n_pairs * wl.n_points * wl.n_surrogates * wl.n_trials:
                 raise ValueError("perms must be [n_pairs, n_points, S, n_trials]")
@@ -387,9 +427,10 @@ def tune_clear():
     check(lib().te_tune_clear())
 
 
-def profile_enable(on: bool = True):
-    """Bracket search-kernel launches with HIP events (te_profile_enable)."""
-    check(lib().te_profile_enable(int(bool(on))))
+def profile_enable(on: bool = True, work: bool = False):
+    """te_profile_enable: on brackets search-kernel launches with HIP events; work makes the
+    launches count the pairs they evaluate (profile_work)."""
+    check(lib().te_profile_enable((1 if on else 0) | (2 if work else 0)))
 
 
 def profile_read(reset: bool = False):

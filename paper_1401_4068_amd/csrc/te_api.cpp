@@ -157,10 +157,8 @@ void Batch::finish_layout()
     o = align_up(o + sizeof(int32_t) * item_start.size(), 16);
     off_tasks = o;
     o = align_up(o + sizeof(EmbedTask) * tasks.size(), 16);
-    off_prow = o;
-    o = align_up(o + sizeof(int64_t) * perm_rows.size(), 16);
-    off_prc = o;
-    o = align_up(o + sizeof(int32_t) * perm_rc.size(), 16);
+    off_ptasks = o;
+    o = align_up(o + sizeof(PermTask) * perm_tasks.size(), 16);
     off_sorts = o;
     o = align_up(o + sizeof(SortTask) * sorts.size(), 16);
     off_parts = o;
@@ -182,6 +180,8 @@ void Batch::finish_layout()
     o = off_qctr + sizeof(int32_t) * kQueues;
     off_sigma = align_up(o, 256);
     o = off_sigma + sizeof(int32_t) * (size_t)n_sigma;
+    off_perm = align_up(o, 256);
+    o = off_perm + sizeof(int32_t) * (size_t)n_perm;
     off_scratch = align_up(o, 256);
     o = off_scratch + sizeof(uint64_t) * (size_t)n_scratch;
     total_bytes = align_up(o, 256);
@@ -192,11 +192,9 @@ void Batch::finish_layout()
                 sizeof(int32_t) * item_start.size());
     if (!tasks.empty())
         std::memcpy(host_tables.data() + (off_tasks - off_tables), tasks.data(), sizeof(EmbedTask) * tasks.size());
-    if (!perm_rows.empty()) {
-        std::memcpy(host_tables.data() + (off_prow - off_tables), perm_rows.data(),
-                    sizeof(int64_t) * perm_rows.size());
-        std::memcpy(host_tables.data() + (off_prc - off_tables), perm_rc.data(), sizeof(int32_t) * perm_rc.size());
-    }
+    if (!perm_tasks.empty())
+        std::memcpy(host_tables.data() + (off_ptasks - off_tables), perm_tasks.data(),
+                    sizeof(PermTask) * perm_tasks.size());
     if (!sorts.empty())
         std::memcpy(host_tables.data() + (off_sorts - off_tables), sorts.data(), sizeof(SortTask) * sorts.size());
     std::memcpy(host_tables.data() + (off_parts - off_tables), part_start.data(), sizeof(int32_t) * part_start.size());
@@ -296,9 +294,19 @@ te_status Plan::build_group_batch(const std::vector<int> &groups, int n_surr, Ba
             if (opt.delay_from_device)
                 t.u_slot = gi + 1;
             if (s > 0 && !opt.delays) {
-                t.perm = (((int64_t)pair * p.n_points + c) * n_surr + (s - 1)) * p.n_trials;
-                b->perm_rows.push_back(t.perm);
-                b->perm_rc.push_back(trials[c]);
+                // the surrogate's trial permutation: row (pair, c, s-1) of the caller's
+                // [pair][point][surrogate][trial] array, or drawn from the seed
+                PermTask pt{};
+                pt.src = (((int64_t)pair * p.n_points + c) * n_surr + (s - 1)) * p.n_trials;
+                pt.dst = b->n_perm;
+                pt.rc = trials[c];
+                pt.len = trials[c];
+                pt.pair = pair;
+                pt.point = c;
+                pt.surr = s - 1;
+                b->perm_tasks.push_back(pt);
+                b->n_perm += trials[c];
+                t.perm = pt.dst;
             }
             t.pair = pair;
             t.w = wstart[c];
@@ -404,12 +412,13 @@ te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, co
     if ((e = launch_fill_i32(ctr, 0, 4 + kQueues, st)) != hipSuccess)
         return hip_fail(e, "fill");
     float *base = reinterpret_cast<float *>(ws + b.off_coords);
-    if (!b.perm_rows.empty()) {
-        e = launch_check_perms(perms, reinterpret_cast<const int64_t *>(ws + b.off_prow),
-                               reinterpret_cast<const int32_t *>(ws + b.off_prc), (int)b.perm_rows.size(), ctr + 1,
-                               st);
+    int32_t *parea = reinterpret_cast<int32_t *>(ws + b.off_perm);
+    if (!b.perm_tasks.empty()) {
+        // the caller's permutations (copied and checked) or ones drawn from the seed
+        e = launch_perms(perms, reinterpret_cast<const PermTask *>(ws + b.off_ptasks), (int)b.perm_tasks.size(),
+                         parea, p.seed, ctr + 1, st);
         if (e != hipSuccess)
-            return hip_fail(e, "check_perms launch");
+            return hip_fail(e, "permutation launch");
     }
     int32_t *sigma = reinterpret_cast<int32_t *>(ws + b.off_sigma);
     e = launch_sort(y, nullptr, reinterpret_cast<const SortTask *>(ws + b.off_sorts), (int)b.sorts.size(), sigma,
@@ -419,7 +428,7 @@ te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, co
     int max_n = 0;
     for (const EmbedTask &t : b.tasks)
         max_n = std::max(max_n, t.n);
-    e = launch_embed(x, y, perms, sigma, u_dev, reinterpret_cast<const EmbedTask *>(ws + b.off_tasks),
+    e = launch_embed(x, y, parea, sigma, u_dev, reinterpret_cast<const EmbedTask *>(ws + b.off_tasks),
                      (int)b.tasks.size(), max_n, base, p.n_trials, p.n_samples, p.d_y, p.d_x, p.tau, p.u,
                      p.cond_source, ctr + 1, st);
     if (e != hipSuccess)
@@ -572,16 +581,8 @@ te_status te_plan_create(const te_problem *pr, te_plan *out)
         mn = std::max(mn, one.total_bytes);
     }
     P.min_bytes = mn;
-    // plain path: one window at a time, originals only
-    int64_t maxn = *std::max_element(P.npts.begin(), P.npts.end());
-    P.plain_bytes = align_up(sizeof(float) * (size_t)maxn * (1 + p.d_y + p.d_x + p.cond_source), 256) +
-                    align_up(sizeof(double) * (size_t)((maxn + kWave - 1) / kWave), 256) +
-                    align_up(sizeof(double) * (size_t)p.n_pairs * p.n_points, 256) +
-                    align_up(sizeof(int32_t) * 4 * (size_t)p.n_pairs * p.n_points + 16, 256) +
-                    align_up((sizeof(ChunkDesc) + sizeof(EmbedTask) + sizeof(SortTask) + 16) * (size_t)p.n_pairs *
-                                 p.n_points, 256) +
-                    align_up(sizeof(int32_t) * (size_t)maxn, 256) + sizeof(uint64_t) * (size_t)sort_npad((int)maxn) +
-                    4096;
+    // plain paths: one chunk at a time (te_estimate: originals; te_estimate_each: all chunks)
+    P.plain_bytes = std::max(P.plain_layout(0).total, P.plain_layout(p.n_surrogates).total);
     *out = plan.release();
     return TE_OK;
 }
@@ -615,7 +616,24 @@ te_status te_estimate(te_plan plan, const float *x, const float *y, void *ws, si
     te_status s = plan->impl.ensure_device();
     if (s != TE_OK)
         return s;
-    return plan->impl.estimate_plain(x, y, static_cast<char *>(ws), ws_bytes, (hipStream_t)hip_stream, te_out);
+    return plan->impl.estimate_each(x, y, nullptr, 0, static_cast<char *>(ws), ws_bytes, (hipStream_t)hip_stream,
+                                    te_out, nullptr, nullptr);
+}
+
+te_status te_estimate_each(te_plan plan, const float *x, const float *y, const int32_t *perms, void *ws,
+                           size_t ws_bytes, void *hip_stream, double *te_orig, double *te_surr, double *p_value)
+{
+    clear_error();
+    if (!plan || !x || !y || !ws || !te_orig)
+        return fail(TE_ERR_INVALID, "null argument");
+    const Plan &P = plan->impl;
+    if (P.p.n_surrogates > 0 && !te_surr)
+        return fail(TE_ERR_INVALID, "n_surrogates > 0 needs te_surr");
+    te_status s = P.ensure_device();
+    if (s != TE_OK)
+        return s;
+    return P.estimate_each(x, y, perms, P.p.n_surrogates, static_cast<char *>(ws), ws_bytes, (hipStream_t)hip_stream,
+                           te_orig, te_surr, p_value);
 }
 
 te_status te_surrogates(te_plan plan, const float *x, const float *y, const int32_t *perms, void *ws,
@@ -626,8 +644,8 @@ te_status te_surrogates(te_plan plan, const float *x, const float *y, const int3
     if (!plan || !x || !y || !ws || !te_orig)
         return fail(TE_ERR_INVALID, "null argument");
     const Plan &P = plan->impl;
-    if (P.p.n_surrogates > 0 && (!perms || !te_surr))
-        return fail(TE_ERR_INVALID, "n_surrogates > 0 needs perms and te_surr");
+    if (P.p.n_surrogates > 0 && !te_surr)
+        return fail(TE_ERR_INVALID, "n_surrogates > 0 needs te_surr");
     te_status s = plan->impl.ensure_device();
     if (s != TE_OK)
         return s;
@@ -642,12 +660,65 @@ te_status te_surrogates_async(te_plan plan, const float *x, const float *y, cons
     if (!plan || !x || !y || !ws || !out)
         return fail(TE_ERR_INVALID, "null argument");
     const Plan &P = plan->impl;
-    if (P.p.n_surrogates > 0 && !perms)
-        return fail(TE_ERR_INVALID, "n_surrogates > 0 needs perms");
     te_status s = P.ensure_device();
     if (s != TE_OK)
         return s;
     return P.run_surrogates_async(x, y, perms, static_cast<char *>(ws), ws_bytes, (hipStream_t)hip_stream, out);
+}
+
+size_t te_plan_permutations_workspace_bytes(te_plan plan)
+{
+    if (!plan)
+        return 0;
+    return align_up(sizeof(PermTask) * plan->impl.full.perm_tasks.size(), 256) + 256;
+}
+
+te_status te_plan_permutations(te_plan plan, void *ws, size_t ws_bytes, void *hip_stream, int32_t *perms)
+{
+    clear_error();
+    if (!plan || !ws || !perms)
+        return fail(TE_ERR_INVALID, "null argument");
+    const Plan &P = plan->impl;
+    const std::vector<PermTask> &rows = P.full.perm_tasks;
+    if (rows.empty())
+        return TE_OK;
+    const size_t need = te_plan_permutations_workspace_bytes(plan);
+    if (ws_bytes < need)
+        return fail(TE_ERR_NOMEM, "te_plan_permutations needs a workspace of %zu bytes", need);
+    te_status s = P.ensure_device();
+    if (s != TE_OK)
+        return s;
+    // every row at its place in the caller's [pair][point][surrogate][trial] array
+    const size_t tbytes = sizeof(PermTask) * rows.size();
+    char *stg = static_cast<char *>(P.pool.take(tbytes + 64));
+    if (!stg)
+        return fail(TE_ERR_NOMEM, "pinned staging allocation failed");
+    PermTask *ht = reinterpret_cast<PermTask *>(stg);
+    for (size_t i = 0; i < rows.size(); ++i) {
+        ht[i] = rows[i];
+        ht[i].dst = rows[i].src;
+        ht[i].len = P.p.n_trials;
+    }
+    char *d = static_cast<char *>(ws);
+    int32_t *err = reinterpret_cast<int32_t *>(d + need - 256);
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipError_t e = hipMemcpyAsync(d, stg, tbytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = launch_fill_i32(err, 0, 1, st);
+    if (e == hipSuccess)
+        e = launch_perms(nullptr, reinterpret_cast<const PermTask *>(d), (int)rows.size(), perms, P.p.seed, err, st);
+    int32_t *herr = reinterpret_cast<int32_t *>(stg + tbytes);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    const int32_t bad = e == hipSuccess ? *herr : 0;
+    P.pool.give(stg);
+    if (e != hipSuccess)
+        return hip_fail(e, "te_plan_permutations");
+    if (bad)
+        return fail(TE_ERR_DEVICE, "permutation draw failed (more rejected draws than the kernel records)");
+    return TE_OK;
 }
 
 te_status te_plan_local_offsets(te_plan plan, int64_t *offsets)

@@ -186,6 +186,8 @@ te_status Plan::run_surrogates(const float *x, const float *y, const int32_t *pe
     }
     if (s == TE_OK && (e = hipStreamSynchronize(st)) != hipSuccess)
         s = hip_fail(e, "hipStreamSynchronize");
+    if (s != TE_OK)
+        hipStreamSynchronize(st);           // queued copies may still read the staging buffers
     bool bad = false;
     if (s == TE_OK)
         for (size_t i = 0; i < batches->size(); ++i)
@@ -256,64 +258,76 @@ te_status Plan::run_local(const float *x, const float *y, char *ws, size_t ws_by
     return TE_OK;
 }
 
-// Plain path: each (pair, window) on its own -- embed, search, reduce -- in
-// window order on one stream; all estimates are copied back at the end.
-te_status Plan::estimate_plain(const float *x, const float *y, char *ws, size_t ws_bytes, hipStream_t st,
-                               double *te_out) const
+// Layout of the plain per-chunk path's workspace for n_surr surrogates per window:
+// one chunk's coordinates (the target block, then one source block), partial sums,
+// results [group][original, surrogates] and p-values, per-launch counters, the
+// tables, the window's sort map, its surrogates' permutation rows, sort scratch.
+PlainLayout Plan::plain_layout(int n_surr) const
 {
-    if (ws_bytes < plain_bytes)
-        return fail(TE_ERR_NOMEM, "workspace %zu bytes < plain-path size %zu", ws_bytes, plain_bytes);
-    const int G = p.n_pairs * p.n_points;
+    PlainLayout L;
+    const int64_t G = (int64_t)p.n_pairs * p.n_points;
     const int D = 1 + p.d_y + p.d_x + p.cond_source;
     const int64_t maxn = *std::max_element(npts.begin(), npts.end());
+    const int64_t maxr = *std::max_element(trials.begin(), trials.end());
+    const int64_t C = G * (n_surr + 1);
     size_t o = 0;
-    const size_t off_coords = o;
+    L.coords = o;
     o = align_up(o + sizeof(float) * (size_t)maxn * D, 256);
-    const size_t off_partial = o;
+    L.partial = o;
     o = align_up(o + sizeof(double) * (size_t)((maxn + kWave - 1) / kWave), 256);
-    const size_t off_results = o;
+    L.results = o;
+    o = o + sizeof(double) * (size_t)C;
+    L.pv = o;
     o = align_up(o + sizeof(double) * (size_t)G, 256);
-    const size_t off_ctr = o;
-    o = align_up(o + sizeof(int32_t) * 4 * (size_t)G + 16, 256);
-    const size_t off_tables = o;
-    const size_t tbl_chunks = 0;
-    const size_t tbl_items = align_up(sizeof(ChunkDesc) * G, 16);
-    const size_t tbl_tasks = tbl_items + align_up(sizeof(int32_t) * G, 16);
-    const size_t tbl_sorts = tbl_tasks + align_up(sizeof(EmbedTask) * G, 16);
-    const size_t tbl_bytes = tbl_sorts + sizeof(SortTask) * G;
-    o = align_up(o + tbl_bytes, 256);
-    const size_t off_sigma = o;                       // one window's map, reused window after window
+    L.ctr = o;
+    o = align_up(o + sizeof(int32_t) * 4 * (size_t)C + 16, 256);
+    L.tables = o;
+    L.t_chunks = 0;
+    L.t_items = align_up(sizeof(ChunkDesc) * C, 16);
+    L.t_tasks = L.t_items + align_up(sizeof(int32_t) * C, 16);
+    L.t_sorts = L.t_tasks + align_up(sizeof(EmbedTask) * C, 16);
+    L.t_perms = L.t_sorts + align_up(sizeof(SortTask) * G, 16);
+    L.tables_bytes = L.t_perms + sizeof(PermTask) * (size_t)G * n_surr;
+    o = align_up(o + L.tables_bytes, 256);
+    L.sigma = o;
     o = align_up(o + sizeof(int32_t) * (size_t)maxn, 256);
-    const size_t off_scratch = o;
+    L.perm = o;
+    o = align_up(o + sizeof(int32_t) * (size_t)maxr * n_surr, 256);
+    L.scratch = o;
     o = align_up(o + sizeof(uint64_t) * (size_t)sort_npad((int)maxn), 256);
-    if (o > ws_bytes)
-        return fail(TE_ERR_NOMEM, "plain-path layout needs %zu bytes, workspace has %zu", o, ws_bytes);
+    L.total = o + 4096;
+    return L;
+}
 
-    const size_t out_off = align_up(tbl_bytes, 256);
-    char *stg = static_cast<char *>(pool.take(out_off + sizeof(double) * G + sizeof(int32_t) * 4 * G));
+// Plain path: each (pair, window) on its own and each of its chunks on its own --
+// the window sorted once, then per chunk embed, search and reduce (three launches)
+// -- in window order on one stream; the estimates, p-values and error words are
+// copied back at the end.  n_surr = 0: originals only (te_estimate).
+te_status Plan::estimate_each(const float *x, const float *y, const int32_t *perms, int n_surr, char *ws,
+                              size_t ws_bytes, hipStream_t st, double *te_orig, double *te_surr,
+                              double *p_value) const
+{
+    const PlainLayout L = plain_layout(n_surr);
+    if (ws_bytes < L.total)
+        return fail(TE_ERR_NOMEM, "workspace %zu bytes < plain-path size %zu", ws_bytes, L.total);
+    const int G = p.n_pairs * p.n_points;
+    const int S1 = n_surr + 1;
+    const int64_t C = (int64_t)G * S1;
+    const size_t out_off = align_up(L.tables_bytes, 256);
+    const size_t out_bytes = sizeof(double) * (size_t)(C + G) + sizeof(int32_t) * 4 * (size_t)C;
+    char *stg = static_cast<char *>(pool.take(out_off + out_bytes));
     if (!stg)
         return fail(TE_ERR_NOMEM, "pinned staging allocation failed");
-    ChunkDesc *hc = reinterpret_cast<ChunkDesc *>(stg + tbl_chunks);
-    int32_t *hi = reinterpret_cast<int32_t *>(stg + tbl_items);
-    EmbedTask *ht = reinterpret_cast<EmbedTask *>(stg + tbl_tasks);
-    SortTask *hs = reinterpret_cast<SortTask *>(stg + tbl_sorts);
+    ChunkDesc *hc = reinterpret_cast<ChunkDesc *>(stg + L.t_chunks);
+    int32_t *hi = reinterpret_cast<int32_t *>(stg + L.t_items);
+    EmbedTask *ht = reinterpret_cast<EmbedTask *>(stg + L.t_tasks);
+    SortTask *hs = reinterpret_cast<SortTask *>(stg + L.t_sorts);
+    PermTask *hp = reinterpret_cast<PermTask *>(stg + L.t_perms);
     const int dT = 1 + p.d_y + p.cond_source;     // x_t, when conditioned on, is the last target-past row
+    const bool cond = p.cond_source != 0;
     for (int g = 0; g < G; ++g) {
         const int pair = g / p.n_points, c = g % p.n_points;
         const int N = (int)npts[c];
-        ChunkDesc d{};
-        d.tp = 0;
-        d.s = (int64_t)dT * N;
-        d.ld = N;
-        d.out = -1;
-        d.perm = -1;
-        d.n = N;
-        d.item0 = 0;
-        d.block0 = 0;
-        d.pbase = 0;
-        d.result = g;
-        hc[g] = d;
-        hi[g] = 0;
         SortTask so{};
         so.sig = 0;
         so.npad = sort_npad(N);
@@ -326,77 +340,122 @@ te_status Plan::estimate_plain(const float *x, const float *y, char *ws, size_t 
         so.Rc = trials[c];
         so.n = N;
         hs[g] = so;
-        EmbedTask t{};
-        t.tp = 0;
-        t.s = (int64_t)dT * N;
-        t.perm = -1;
-        t.sig = sorted ? 0 : -1;
-        t.pair = pair;
-        t.w = wstart[c];
-        t.W = wlen[c];
-        t.Rc = trials[c];
-        t.n = N;
-        ht[g] = t;
+        for (int s = 0; s < S1; ++s) {
+            const int64_t ci = (int64_t)g * S1 + s;
+            ChunkDesc d{};
+            d.tp = 0;
+            d.s = (int64_t)dT * N;
+            d.ld = N;
+            d.out = -1;
+            d.perm = -1;
+            d.n = N;
+            d.result = (int32_t)ci;
+            hc[ci] = d;
+            hi[ci] = 0;
+            EmbedTask t{};
+            // the target block is written with the original and kept for its surrogates
+            // (with x_t conditioned on, every chunk writes its own: x_t follows the shuffle)
+            t.tp = (s == 0 || cond) ? 0 : -1;
+            t.s = (int64_t)dT * N;
+            t.perm = -1;
+            t.sig = sorted ? 0 : -1;
+            t.pair = pair;
+            t.w = wstart[c];
+            t.W = wlen[c];
+            t.Rc = trials[c];
+            t.n = N;
+            if (s > 0) {
+                PermTask pt{};
+                pt.src = (((int64_t)pair * p.n_points + c) * n_surr + (s - 1)) * p.n_trials;
+                pt.dst = (int64_t)(s - 1) * trials[c];
+                pt.rc = trials[c];
+                pt.len = trials[c];
+                pt.pair = pair;
+                pt.point = c;
+                pt.surr = s - 1;
+                hp[(int64_t)g * n_surr + (s - 1)] = pt;
+                t.perm = pt.dst;
+            }
+            ht[ci] = t;
+        }
     }
-    hipError_t e = hipMemcpyAsync(ws + off_tables, stg, tbl_bytes, hipMemcpyHostToDevice, st);
-    int32_t *ctr = reinterpret_cast<int32_t *>(ws + off_ctr);
+    hipError_t e = hipMemcpyAsync(ws + L.tables, stg, L.tables_bytes, hipMemcpyHostToDevice, st);
+    int32_t *ctr = reinterpret_cast<int32_t *>(ws + L.ctr);
     if (e == hipSuccess)
-        e = launch_fill_i32(ctr, 0, 4 * (int64_t)G, st);
-    float *base = reinterpret_cast<float *>(ws + off_coords);
-    double *partial = reinterpret_cast<double *>(ws + off_partial);
-    double *res = reinterpret_cast<double *>(ws + off_results);
-    const ChunkDesc *dc = reinterpret_cast<const ChunkDesc *>(ws + off_tables + tbl_chunks);
-    const int32_t *di = reinterpret_cast<const int32_t *>(ws + off_tables + tbl_items);
-    const EmbedTask *dt = reinterpret_cast<const EmbedTask *>(ws + off_tables + tbl_tasks);
-    const SortTask *ds = reinterpret_cast<const SortTask *>(ws + off_tables + tbl_sorts);
-    int32_t *sigma = reinterpret_cast<int32_t *>(ws + off_sigma);
-    uint64_t *scratch = reinterpret_cast<uint64_t *>(ws + off_scratch);
+        e = launch_fill_i32(ctr, 0, 4 * C, st);
+    float *base = reinterpret_cast<float *>(ws + L.coords);
+    double *partial = reinterpret_cast<double *>(ws + L.partial);
+    double *res = reinterpret_cast<double *>(ws + L.results);
+    double *pv = reinterpret_cast<double *>(ws + L.pv);
+    const ChunkDesc *dc = reinterpret_cast<const ChunkDesc *>(ws + L.tables + L.t_chunks);
+    const int32_t *di = reinterpret_cast<const int32_t *>(ws + L.tables + L.t_items);
+    const EmbedTask *dt = reinterpret_cast<const EmbedTask *>(ws + L.tables + L.t_tasks);
+    const SortTask *ds = reinterpret_cast<const SortTask *>(ws + L.tables + L.t_sorts);
+    const PermTask *dp = reinterpret_cast<const PermTask *>(ws + L.tables + L.t_perms);
+    int32_t *sigma = reinterpret_cast<int32_t *>(ws + L.sigma);
+    int32_t *parea = reinterpret_cast<int32_t *>(ws + L.perm);
+    uint64_t *scratch = reinterpret_cast<uint64_t *>(ws + L.scratch);
     for (int g = 0; g < G && e == hipSuccess; ++g) {
         const int c = g % p.n_points;
         const int64_t items = (npts[c] + kWave - 1) / kWave;
-        if (sorted) {
-            e = launch_sort(y, nullptr, ds + g, 1, sigma, scratch, p.n_trials, p.n_samples, st);
+        int32_t *gerr = ctr + 4 * (int64_t)g * S1 + 1;   // the window's error word: its original's
+        if (sorted && (e = launch_sort(y, nullptr, ds + g, 1, sigma, scratch, p.n_trials, p.n_samples, st)) !=
+                          hipSuccess)
+            break;
+        if (n_surr > 0 &&
+            (e = launch_perms(perms, dp + (int64_t)g * n_surr, n_surr, parea, p.seed, gerr, st)) != hipSuccess)
+            break;
+        for (int s = 0; s < S1 && e == hipSuccess; ++s) {
+            const int64_t ci = (int64_t)g * S1 + s;
+            e = launch_embed(x, y, parea, sigma, nullptr, dt + ci, 1, (int)npts[c], base, p.n_trials, p.n_samples,
+                             p.d_y, p.d_x, p.tau, p.u, p.cond_source, gerr, st);
             if (e != hipSuccess)
                 break;
+            SearchArgs a{};
+            a.base = base;
+            a.chunks = dc + ci;
+            a.item_start = di + ci;
+            a.n_chunks = 1;
+            a.n_items = (int32_t)items;
+            a.k = p.k;
+            a.counter = ctr + 4 * ci;
+            a.partial = partial;
+            a.sorted = sorted ? 1 : 0;
+            e = launch_search_timed(a, dy_eff(), p.d_x, cfg, grid_waves(items), st);
+            if (e == hipSuccess)
+                e = launch_reduce(dc + ci, 1, partial, p.k, gerr, res, st);
         }
-        e = launch_embed(x, y, nullptr, sigma, nullptr, dt + g, 1, (int)npts[g % p.n_points], base, p.n_trials,
-                         p.n_samples, p.d_y, p.d_x, p.tau, p.u, p.cond_source, ctr + 4 * g + 1, st);
-        if (e != hipSuccess)
-            break;
-        SearchArgs a{};
-        a.base = base;
-        a.chunks = dc + g;
-        a.item_start = di + g;
-        a.n_chunks = 1;
-        a.n_items = (int32_t)items;
-        a.k = p.k;
-        a.counter = ctr + 4 * g;
-        a.partial = partial;
-        a.sorted = sorted ? 1 : 0;
-        e = launch_search_timed(a, dy_eff(), p.d_x, cfg, grid_waves(items), st);
-        if (e != hipSuccess)
-            break;
-        e = launch_reduce(dc + g, 1, partial, p.k, ctr + 4 * g + 1, res, st);
     }
+    if (e == hipSuccess && n_surr > 0)
+        e = launch_pvalues(res, G, n_surr, pv, st);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(stg + out_off, res, sizeof(double) * G, hipMemcpyDeviceToHost, st);
+        e = hipMemcpyAsync(stg + out_off, res, sizeof(double) * (size_t)(C + G), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(stg + out_off + sizeof(double) * G, ctr, sizeof(int32_t) * 4 * G, hipMemcpyDeviceToHost,
-                           st);
+        e = hipMemcpyAsync(stg + out_off + sizeof(double) * (C + G), ctr, sizeof(int32_t) * 4 * C,
+                           hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
         e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
+        hipStreamSynchronize(st);
         pool.give(stg);
         return hip_fail(e, "plain path");
     }
-    std::memcpy(te_out, stg + out_off, sizeof(double) * G);
-    const int32_t *errs = reinterpret_cast<const int32_t *>(stg + out_off + sizeof(double) * G);
+    const double *hr = reinterpret_cast<const double *>(stg + out_off);
+    const int32_t *errs = reinterpret_cast<const int32_t *>(stg + out_off + sizeof(double) * (C + G));
     bool bad = false;
-    for (int g = 0; g < G; ++g)
-        bad |= errs[4 * g + 1] != 0;
+    for (int g = 0; g < G; ++g) {
+        bad |= errs[4 * (int64_t)g * S1 + 1] != 0;
+        if (te_orig)
+            te_orig[g] = hr[(int64_t)g * S1];
+        if (te_surr)
+            for (int s = 0; s < n_surr; ++s)
+                te_surr[(int64_t)g * n_surr + s] = hr[(int64_t)g * S1 + 1 + s];
+        if (p_value)
+            p_value[g] = n_surr > 0 ? hr[C + g] : __builtin_nan("");
+    }
     pool.give(stg);
     if (bad)
-        return fail(TE_ERR_INVALID, "non-finite input value");
+        return fail(TE_ERR_INVALID, "non-finite input value or invalid surrogate permutation");
     return TE_OK;
 }
 

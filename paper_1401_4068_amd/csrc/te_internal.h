@@ -37,13 +37,26 @@ struct ChunkDesc {
 struct EmbedTask {
     int64_t tp;       // float offset of the target block, or -1
     int64_t s;        // float offset of the source block
-    int64_t perm;     // int32 offset of the source permutation row, or -1 (identity)
+    int64_t perm;     // int32 offset of the source permutation row in the batch's permutation area, or -1 (identity)
     int64_t sig;      // int32 offset of the window's sorted-to-original point map, or -1 (identity)
     int32_t pair, w, W, Rc;
     int32_t n;        // Rc * W
     int32_t u;        // source delay of this block; 0: the launch's delay
     int32_t u_slot;   // > 0: the delay is read on the device from u_dev[u_slot - 1] (overrides u)
     int32_t pad_;
+};
+
+// One surrogate's trial permutation in a batch's permutation area.  It is either
+// copied from the caller's [pair][point][surrogate][trial] array (and checked to
+// be a permutation of 0..rc-1) or drawn on the device from the problem's seed,
+// keyed by (pair, point, surr).  Entries rc..len-1 of a written row are the
+// identity.
+struct PermTask {
+    int64_t src;      // int32 offset of the row in the caller's array (copy mode)
+    int64_t dst;      // int32 offset of the row in the destination
+    int32_t rc;       // trials pooled by the window: the row permutes 0..rc-1
+    int32_t len;      // entries written (>= rc)
+    int32_t pair, point, surr, pad_;
 };
 
 // Sorting of one search space by its first target-past coordinate p0.  The
@@ -115,8 +128,10 @@ hipError_t launch_sort(const float *y, const float *pts, const SortTask *tasks, 
                        uint64_t *scratch, int R, int T, hipStream_t st);
 hipError_t launch_gather(const float *src, const GatherTask *tasks, int n_tasks, const int32_t *sigma, float *dst,
                          int D, hipStream_t st);
-hipError_t launch_check_perms(const int32_t *perms, const int64_t *rows, const int32_t *rc, int n_rows,
-                              int32_t *err, hipStream_t st);
+// Fill a batch's permutation area: copy (and check) the caller's rows when src is
+// given, else draw every row from `seed`.  Sets bit 2 of *err for an invalid row.
+hipError_t launch_perms(const int32_t *src, const PermTask *tasks, int n_tasks, int32_t *dst,
+                        uint64_t seed, int32_t *err, hipStream_t st);
 hipError_t launch_search(const SearchArgs &a, int d_y, int d_x, const SearchConfig &cfg, int grid_waves,
                          hipStream_t st);
 // With pv != nullptr the launch also computes the n_groups p-values (results laid

@@ -226,6 +226,7 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
     int qp = (int)(blockIdx.x % (unsigned)nq);   // this wave's queue
     int drained = 0;                              // queues found empty so far
     int last_ci = 0, last_lo = 0, last_hi = 0;    // the previous item's chunk and its item range
+    unsigned long long work1 = 0, work2 = 0;      // pairs this wave evaluated in pass 1 / pass 2
     for (;;) {
         // ---- claim the next work item (wave-uniform)
         int q = 0;
@@ -627,13 +628,10 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
         if (valid)
             term = psi_of_count(nP) - psi_of_count(nTP) - psi_of_count(nPS);
         const double sum = wave_sum(term);
-        if (lane == 0) {
+        if (lane == 0)
             a.partial[cd.pbase + blk] = sum;
-            if (a.work != nullptr) {
-                atomicAdd(a.work, (unsigned long long)visited * (unsigned long long)nref);
-                atomicAdd(a.work + 1, evaluated2);
-            }
-        }
+        work1 += (unsigned long long)visited * (unsigned long long)nref;
+        work2 += evaluated2;
         if (a.lte_out != nullptr && cd.out >= 0 && valid) {
             int o = (cd.perm >= 0) ? a.perm_base[cd.perm + i] : i;
             if (o < 0 || o >= n)
@@ -650,6 +648,11 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
             a.cnt_out[a.cnt_stride + cd.out + o] = nTP;
             a.cnt_out[2 * a.cnt_stride + cd.out + o] = nPS;
         }
+    }
+    // measurement: one pair of counter updates per wave, after its last item
+    if (a.work != nullptr && lane == 0) {
+        atomicAdd(a.work, work1);
+        atomicAdd(a.work + 1, work2);
     }
 }
 
@@ -1000,36 +1003,195 @@ __global__ void gather_kernel(const float *__restrict__ src, const GatherTask *_
     }
 }
 
-// Permutation rows must be permutations of 0..Rc-1: one workgroup per row,
-// an LDS bitmap records which values were seen.
+// ------------------------------------------------------ surrogate permutations
+
 constexpr int kMaxPermTrials = 1 << 16;
 
-__global__ void check_perms_kernel(const int32_t *__restrict__ perms, const int64_t *__restrict__ rows,
-                                   const int32_t *__restrict__ rc, int32_t *err)
+// Copy mode: row i of the caller's permutations into the batch's permutation
+// area.  Entries < rc must be a permutation of 0..rc-1 (one workgroup per row,
+// an LDS bitmap records the values seen); entries rc..len-1 are the identity.
+__global__ void take_perms_kernel(const int32_t *__restrict__ src, const PermTask *__restrict__ tasks,
+                                  int32_t *__restrict__ dst, int32_t *err)
 {
     __shared__ uint32_t seen[kMaxPermTrials / 32];
-    const int Rc = rc[blockIdx.x];
-    const int32_t *row = perms + rows[blockIdx.x];
-    const bool too_big = Rc > kMaxPermTrials;
-    const int words = too_big ? 0 : (Rc + 31) / 32;
+    const PermTask tk = tasks[blockIdx.x];
+    const int rc = tk.rc;
+    const bool too_big = rc > kMaxPermTrials || rc < 1;
+    const int words = too_big ? 0 : (rc + 31) / 32;
     for (int w = threadIdx.x; w < words; w += blockDim.x)
         seen[w] = 0;
     __syncthreads();
     bool bad = too_big;
     if (!bad) {
-        for (int r = threadIdx.x; r < Rc; r += blockDim.x) {
-            const int v = row[r];
-            if (v < 0 || v >= Rc) {
+        for (int r = threadIdx.x; r < rc; r += blockDim.x) {
+            const int v = src[tk.src + r];
+            if (v < 0 || v >= rc) {
                 bad = true;
+                dst[tk.dst + r] = r;          // keep later reads in bounds; the call reports the error
             } else {
                 const uint32_t bit = 1u << (v & 31);
                 if (atomicOr(&seen[v >> 5], bit) & bit)
                     bad = true;
+                dst[tk.dst + r] = v;
             }
         }
     }
+    for (int r = max(rc, 0) + threadIdx.x; r < tk.len; r += blockDim.x)
+        dst[tk.dst + r] = r;
     if (bad)
         atomicOr(err, 2);
+}
+
+// Seeded mode.  The permutation of (pair p, point c, surrogate s) is drawn from
+// the counter-based SplitMix64 generator (Steele, Lea and Flood 2014): output q
+// of the stream with key K is mix(K + (q + 1) G), and K folds the identifiers
+// into the seed, K = f(f(f(f(f(0x5EED5EED5EED5EED, seed), 77), p), c), s) with
+// f(k, v) = mix(k + G v + 1).  Fisher-Yates from the top: for i = rc-1 down to 1,
+// swap positions i and j_i, j_i uniform on 0..i.  Draw number t = rc-1-i takes its
+// bound i + 1 and Lemire's multiply-and-reject rule on the high 32 bits w of an
+// output: m = w (i + 1), j_i = m >> 32, rejected when (m mod 2^32) < 2^32 mod (i+1).
+// Draws are made in rounds: in round one draw t takes output t; each later round
+// gives the draws rejected so far, in draw order, the next unused outputs.
+// One wave per row: the rounds run across lanes, the swaps on one lane in LDS
+// (rows of up to kDrawLds trials) or in the destination row itself (longer rows).
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+constexpr int kDrawLds = 8192;
+constexpr int kMaxRejects = 256;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t fold_key(uint64_t k, uint64_t v) { return mix64(k + kGolden * v + 1ull); }
+
+// Lemire's rule for bound s on output q of stream key: the draw, or -1 if rejected.
+__device__ __forceinline__ int lemire_draw(uint64_t key, uint64_t q, uint32_t s)
+{
+    const uint32_t w = (uint32_t)(mix64(key + (q + 1ull) * kGolden) >> 32);
+    const uint64_t m = (uint64_t)w * s;
+    const uint32_t lo = (uint32_t)m;
+    if (lo < s && lo < (0u - s) % s)
+        return -1;
+    return (int)(m >> 32);
+}
+
+__global__ void __launch_bounds__(64) draw_perms_kernel(const PermTask *__restrict__ tasks, int32_t *__restrict__ dst,
+                                                        uint64_t seed, int32_t *err)
+{
+    __shared__ int32_t lds_perm[kDrawLds];
+    __shared__ int32_t pend[2][kMaxRejects];
+    __shared__ int32_t fix_t[kMaxRejects], fix_j[kMaxRejects];
+    const PermTask tk = tasks[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int n = tk.rc;
+    int32_t *row = dst + tk.dst;
+    if (n < 1 || n > kMaxPermTrials) {
+        for (int r = lane; r < tk.len; r += kWave)
+            row[r] = r;
+        if (lane == 0)
+            atomicOr(err, 2);
+        return;
+    }
+    uint64_t key = 0x5EED5EED5EED5EEDull;
+    key = fold_key(key, seed);
+    key = fold_key(key, 77ull);
+    key = fold_key(key, (uint64_t)(int64_t)tk.pair);
+    key = fold_key(key, (uint64_t)(int64_t)tk.point);
+    key = fold_key(key, (uint64_t)(int64_t)tk.surr);
+    const int draws = n - 1;
+    const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+    // round one: find the rejected draws (rare), in draw order
+    int npend = 0;
+    for (int t0 = 0; t0 < draws; t0 += kWave) {
+        const int t = t0 + lane;
+        const bool rej = t < draws && lemire_draw(key, (uint64_t)t, (uint32_t)(n - t)) < 0;
+        const uint64_t mask = ballot(rej);
+        if (rej) {
+            const int idx = npend + __builtin_popcountll(mask & lanes_below);
+            if (idx < kMaxRejects)
+                pend[0][idx] = t;
+        }
+        npend += __builtin_popcountll(mask);
+    }
+    bool overflow = npend > kMaxRejects;
+    // later rounds: pending draws take the next unused outputs, in draw order
+    uint64_t pos = (uint64_t)max(draws, 0);
+    int nfix = 0, cur = 0;
+    while (npend > 0 && !overflow) {
+        __builtin_amdgcn_wave_barrier();
+        int nnext = 0;
+        for (int b0 = 0; b0 < npend; b0 += kWave) {
+            const int l = b0 + lane;
+            int t = 0, j = -1;
+            if (l < npend) {
+                t = pend[cur][l];
+                j = lemire_draw(key, pos + (uint64_t)l, (uint32_t)(n - t));
+            }
+            const bool acc = l < npend && j >= 0;
+            const bool rej = l < npend && j < 0;
+            const uint64_t ma = ballot(acc), mr = ballot(rej);
+            if (acc) {
+                const int idx = nfix + __builtin_popcountll(ma & lanes_below);
+                if (idx < kMaxRejects) {
+                    fix_t[idx] = t;
+                    fix_j[idx] = j;
+                }
+            }
+            if (rej) {
+                const int idx = nnext + __builtin_popcountll(mr & lanes_below);
+                if (idx < kMaxRejects)
+                    pend[cur ^ 1][idx] = t;
+            }
+            nfix += __builtin_popcountll(ma);
+            nnext += __builtin_popcountll(mr);
+        }
+        pos += (uint64_t)npend;
+        npend = nnext;
+        cur ^= 1;
+        overflow = nfix > kMaxRejects || npend > kMaxRejects;
+    }
+    if (overflow) {
+        for (int r = lane; r < tk.len; r += kWave)
+            row[r] = r;
+        if (lane == 0)
+            atomicOr(err, 2);
+        return;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // the swaps, in order, on one lane
+    int32_t *a = n <= kDrawLds ? lds_perm : row;
+    for (int r = lane; r < n; r += kWave)
+        a[r] = r;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane == 0) {
+        for (int t = 0; t < draws; ++t) {
+            const int i = n - 1 - t;
+            int j = lemire_draw(key, (uint64_t)t, (uint32_t)(i + 1));
+            if (j < 0)
+                for (int f = 0; f < nfix; ++f)
+                    if (fix_t[f] == t)
+                        j = fix_j[f];
+            if (j < 0 || j > i)              // cannot happen: every rejected draw has a fix
+                j = i;
+            const int32_t vi = a[i], vj = a[j];
+            a[i] = vj;
+            a[j] = vi;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (n <= kDrawLds)
+        for (int r = lane; r < n; r += kWave)
+            row[r] = lds_perm[r];
+    for (int r = n + lane; r < tk.len; r += kWave)
+        row[r] = r;
 }
 
 // p-value of window group g (eq. 10 test): the fraction of its n_surr surrogate
@@ -1252,12 +1414,15 @@ hipError_t launch_gather(const float *src, const GatherTask *tasks, int n_tasks,
     return hipGetLastError();
 }
 
-hipError_t launch_check_perms(const int32_t *perms, const int64_t *rows, const int32_t *rc, int n_rows,
-                              int32_t *err, hipStream_t st)
+hipError_t launch_perms(const int32_t *src, const PermTask *tasks, int n_tasks, int32_t *dst,
+                        uint64_t seed, int32_t *err, hipStream_t st)
 {
-    if (n_rows <= 0)
+    if (n_tasks <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(check_perms_kernel, dim3(n_rows), dim3(256), 0, st, perms, rows, rc, err);
+    if (src != nullptr)
+        hipLaunchKernelGGL(take_perms_kernel, dim3(n_tasks), dim3(256), 0, st, src, tasks, dst, err);
+    else
+        hipLaunchKernelGGL(draw_perms_kernel, dim3(n_tasks), dim3(kWave), 0, st, tasks, dst, seed, err);
     return hipGetLastError();
 }
 

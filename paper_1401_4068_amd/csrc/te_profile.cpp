@@ -13,7 +13,8 @@ namespace te {
 
 namespace {
 std::mutex g_mu;
-bool g_on = false;
+bool g_on = false;        // HIP events around search launches
+bool g_work_on = false;   // device counters of evaluated pairs
 struct Pending {
     hipEvent_t a, b;
 };
@@ -40,16 +41,24 @@ hipEvent_t get_event()
 hipError_t launch_search_timed(const SearchArgs &a, int d_y, int d_x, const SearchConfig &cfg, int grid_waves,
                                hipStream_t st)
 {
-    bool on;
+    bool on, work_on;
     {
         std::lock_guard<std::mutex> lk(g_mu);
         on = g_on;
+        work_on = g_work_on;
     }
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (on && hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
-        on = false;
+    if ((on || work_on) && hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        on = work_on = false;
+    SearchArgs b = a;
+    if (work_on) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!g_work)
+            g_work = work_counters();
+        b.work = g_work;
+    }
     if (!on)
-        return launch_search(a, d_y, d_x, cfg, grid_waves, st);
+        return launch_search(b, d_y, d_x, cfg, grid_waves, st);
     hipEvent_t e0, e1;
     {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -57,14 +66,7 @@ hipError_t launch_search_timed(const SearchArgs &a, int d_y, int d_x, const Sear
         e1 = get_event();
     }
     if (!e0 || !e1)
-        return launch_search(a, d_y, d_x, cfg, grid_waves, st);
-    SearchArgs b = a;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        if (!g_work)
-            g_work = work_counters();
-        b.work = g_work;
-    }
+        return launch_search(b, d_y, d_x, cfg, grid_waves, st);
     hipEventRecord(e0, st);
     hipError_t e = launch_search(b, d_y, d_x, cfg, grid_waves, st);
     hipEventRecord(e1, st);
@@ -82,7 +84,8 @@ extern "C" {
 te_status te_profile_enable(int32_t on)
 {
     std::lock_guard<std::mutex> lk(g_mu);
-    g_on = on != 0;
+    g_on = (on & TE_PROFILE_TIME) != 0;
+    g_work_on = (on & TE_PROFILE_WORK) != 0;
     return TE_OK;
 }
 

@@ -36,16 +36,16 @@ struct Batch {
     std::vector<int> order;
     std::vector<int32_t> item_start;
     std::vector<EmbedTask> tasks;
-    std::vector<int64_t> perm_rows;
-    std::vector<int32_t> perm_rc;
+    std::vector<PermTask> perm_tasks;     // one per surrogate chunk: its trial permutation
+    int64_t n_perm = 0;                   // int32 entries of the batch's permutation area
     std::vector<SortTask> sorts;          // one per window group (empty when chunks are not sorted)
     int64_t n_sigma = 0;                  // int32 entries of the sorted-to-original maps
     int64_t n_scratch = 0;                // uint64 sort scratch entries
     int64_t n_items = 0;
     std::vector<int32_t> part_start;      // [kQueues + 1] item ranges of the XCD work queues
     // byte offsets inside the workspace
-    size_t off_coords = 0, off_tables = 0, off_chunks = 0, off_items = 0, off_tasks = 0, off_prow = 0,
-           off_prc = 0, off_sorts = 0, off_partial = 0, off_results = 0, off_pv = 0, off_ctr = 0, off_sigma = 0,
+    size_t off_coords = 0, off_tables = 0, off_chunks = 0, off_items = 0, off_tasks = 0, off_ptasks = 0,
+           off_perm = 0, off_sorts = 0, off_partial = 0, off_results = 0, off_pv = 0, off_ctr = 0, off_sigma = 0,
            off_scratch = 0, off_parts = 0, off_qctr = 0, off_errout = 0;
     size_t tables_bytes = 0;
     size_t total_bytes = 0;
@@ -85,6 +85,13 @@ struct BatchOptions {
     bool local_outputs = false;                   // per-point local TE of the originals
     const std::vector<int32_t> *delays = nullptr; // variants: the original at each of these source delays
     bool delay_from_device = false;               // source delay of group gi read from u_dev[gi]
+};
+
+// Byte offsets of the plain per-chunk path's workspace (Plan::plain_layout).
+struct PlainLayout {
+    size_t coords = 0, partial = 0, results = 0, pv = 0, ctr = 0, tables = 0, sigma = 0, perm = 0, scratch = 0;
+    size_t t_chunks = 0, t_items = 0, t_tasks = 0, t_sorts = 0, t_perms = 0, tables_bytes = 0;
+    size_t total = 0;
 };
 
 struct Plan {
@@ -135,8 +142,10 @@ struct Plan {
     te_status run_surrogates(const float *x, const float *y, const int32_t *perms, char *ws, size_t ws_bytes,
                              hipStream_t st, bool use_graph, double *te_orig, double *te_surr,
                              double *p_value) const;
-    te_status estimate_plain(const float *x, const float *y, char *ws, size_t ws_bytes, hipStream_t st,
-                             double *te_out) const;
+    PlainLayout plain_layout(int n_surr) const;
+    te_status estimate_each(const float *x, const float *y, const int32_t *perms, int n_surr, char *ws,
+                            size_t ws_bytes, hipStream_t st, double *te_orig, double *te_surr,
+                            double *p_value) const;
 };
 
 }  // namespace te

@@ -215,8 +215,8 @@ te_status te_delay_scan(te_plan plan, const float *x, const float *y, const int3
     if (!plan || !x || !y || !ws || !te_scan)
         return fail(TE_ERR_INVALID, "null argument");
     const Plan &P = plan->impl;
-    if (P.p.n_surrogates > 0 && (!perms || !te_surr))
-        return fail(TE_ERR_INVALID, "n_surrogates > 0 needs perms and te_surr");
+    if (P.p.n_surrogates > 0 && !te_surr)
+        return fail(TE_ERR_INVALID, "n_surrogates > 0 needs te_surr");
     std::vector<int32_t> d;
     te_status s = check_delays(P, u_values, n_u, &d);
     if (s != TE_OK)

@@ -20,6 +20,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <list>
@@ -152,7 +153,17 @@ struct Server {
     DeviceInfo dev;
 
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_done;
+    // The server thread sleeps on cv_wake between state changes: a submission,
+    // cancellation, resume or close, or the device finishing a job's setup or a
+    // step (a host function queued behind that work on its stream).  wake_mu is
+    // never held while a HIP call is made, so the runtime thread that runs those
+    // host functions cannot block on a lock the server thread holds.
+    std::mutex wake_mu;
+    std::condition_variable cv_wake;
+    bool wake = false;
+    int64_t fault_staging = 0;                     // TE_SERVE_FAULT_STAGING: admission that fails its staging
+    int64_t admissions = 0;
     bool stopping = false;
     std::thread thr;
     uint64_t next_id = 1;
@@ -171,6 +182,9 @@ struct Server {
 
     te_status start();
     void loop();
+    void wake_up();
+    void sleep_until_woken(std::unique_lock<std::mutex> &lk, int ms);
+    void drain_streams(const KernelClass *kc);
     int class_of(const te_problem &p, bool sorted);
     bool admit_one(Job *j);
     void poll_setup();
@@ -226,11 +240,15 @@ static int embed_max_n(const Batch &b)
     return m;
 }
 
-static size_t job_footprint(const Plan &P, Batch *b, size_t *off_x, size_t *off_y, size_t *off_perm,
-                            size_t *off_batch)
+// Arena bytes of a job: its series, the caller's permutations (when given; drawn
+// permutations live in the batch's own permutation area), then its batch layout.
+static size_t job_footprint(const Plan &P, bool caller_perms, Batch *b, size_t *off_x, size_t *off_y,
+                            size_t *off_perm, size_t *off_batch)
 {
     const size_t ser = sizeof(float) * (size_t)P.p.n_pairs * P.p.n_trials * P.p.n_samples;
-    const size_t perm = sizeof(int32_t) * (size_t)P.p.n_pairs * P.p.n_points * P.p.n_surrogates * P.p.n_trials;
+    const size_t perm = caller_perms ? sizeof(int32_t) * (size_t)P.p.n_pairs * P.p.n_points * P.p.n_surrogates *
+                                           P.p.n_trials
+                                     : 0;
     size_t o = 0;
     *off_x = o;
     o = align_up(o + ser, 256);
@@ -271,6 +289,45 @@ void Server::release(Job *j)
     resident.remove(j);
 }
 
+// Host function queued behind device work: wakes the server thread.
+static void host_wake(void *srv) { static_cast<Server *>(srv)->wake_up(); }
+
+void Server::wake_up()
+{
+    {
+        std::lock_guard<std::mutex> lk(wake_mu);
+        wake = true;
+    }
+    cv_wake.notify_one();
+}
+
+// Release mu and sleep until woken or ms pass, then take mu again.
+void Server::sleep_until_woken(std::unique_lock<std::mutex> &lk, int ms)
+{
+    lk.unlock();
+    {
+        std::unique_lock<std::mutex> wl(wake_mu);
+        cv_wake.wait_for(wl, std::chrono::milliseconds(ms), [&] { return wake; });
+        wake = false;
+    }
+    lk.lock();
+}
+
+// Wait until the class's streams (every class when kc is null) and the setup
+// stream have run everything queued on them.
+void Server::drain_streams(const KernelClass *kc)
+{
+    if (dry)
+        return;
+    for (const KernelClass &c : classes)
+        if (!kc || &c == kc)
+            for (int sl = 0; sl < 2; ++sl)
+                if (c.stream[sl])
+                    hipStreamSynchronize(c.stream[sl]);
+    if (setup_stream)
+        hipStreamSynchronize(setup_stream);
+}
+
 // Copy the series in, upload the job's tables, embed every chunk once.
 bool Server::admit_one(Job *j)
 {
@@ -284,8 +341,12 @@ bool Server::admit_one(Job *j)
     Batch &b = j->batch;
     j->next_block.assign(b.chunks.size(), 0);
     j->next_chunk = 0;
+    const bool inject = fault_staging > 0 && ++admissions == fault_staging;
     if (dry) {
-        j->state = READY;
+        if (inject)
+            fail_job(j, TE_ERR_NOMEM, "pinned staging allocation failed (injected)");
+        else
+            j->state = READY;
         return true;
     }
     const Plan &P = j->plan->impl;
@@ -309,9 +370,13 @@ bool Server::admit_one(Job *j)
         cd[c].s += fbase;
         cd[c].pbase += pbase;
     }
-    j->stage = pool.take(std::max(b.tables_bytes, sizeof(double) * (b.n_results + b.n_groups) + 64));
+    j->stage = inject ? nullptr : pool.take(std::max(b.tables_bytes, sizeof(double) * (b.n_results + b.n_groups) + 64));
     if (!j->stage) {
-        fail_job(j, TE_ERR_NOMEM, "pinned staging allocation failed");
+        // the series uploads queued above read the pinned inputs and write the job's
+        // region: let them finish before the caller releases either
+        hipStreamSynchronize(setup_stream);
+        fail_job(j, TE_ERR_NOMEM, inject ? "pinned staging allocation failed (injected)"
+                                         : "pinned staging allocation failed");
         return true;
     }
     std::memcpy(j->stage, tables.data(), b.tables_bytes);
@@ -320,11 +385,12 @@ bool Server::admit_one(Job *j)
     int32_t *ctr = reinterpret_cast<int32_t *>(bat + b.off_ctr);
     if (e == hipSuccess)
         e = launch_fill_i32(ctr, 0, 4, setup_stream);
-    const int32_t *perm = reinterpret_cast<const int32_t *>(reg + j->off_perm);
-    if (e == hipSuccess && !b.perm_rows.empty())
-        e = launch_check_perms(perm, reinterpret_cast<const int64_t *>(bat + b.off_prow),
-                               reinterpret_cast<const int32_t *>(bat + b.off_prc), (int)b.perm_rows.size(), ctr + 1,
-                               setup_stream);
+    // the job's permutations: copied (and checked) from the uploaded ones, or drawn from its seed
+    int32_t *perm = reinterpret_cast<int32_t *>(bat + b.off_perm);
+    if (e == hipSuccess && !b.perm_tasks.empty())
+        e = launch_perms(j->n_perm ? reinterpret_cast<const int32_t *>(reg + j->off_perm) : nullptr,
+                         reinterpret_cast<const PermTask *>(bat + b.off_ptasks), (int)b.perm_tasks.size(), perm,
+                         P.p.seed, ctr + 1, setup_stream);
     int32_t *sigma = reinterpret_cast<int32_t *>(bat + b.off_sigma);
     if (e == hipSuccess)
         e = launch_sort(reinterpret_cast<const float *>(reg + j->off_y), nullptr,
@@ -341,8 +407,13 @@ bool Server::admit_one(Job *j)
         e = hipEventRecord(j->ready_ev, setup_stream);
     if (e == hipSuccess)
         e = hipEventCreateWithFlags(&j->done_ev, hipEventDisableTiming);
-    if (e != hipSuccess)
+    if (e == hipSuccess)
+        e = hipLaunchHostFunc(setup_stream, host_wake, this);
+    if (e != hipSuccess) {
+        // work queued before the failure may still be reading or writing the job's memory
+        hipStreamSynchronize(setup_stream);
         fail_job(j, TE_ERR_DEVICE, hipGetErrorString(e));
+    }
     return true;
 }
 
@@ -363,7 +434,7 @@ bool Server::issue_step(int ci)
     KernelClass &kc = classes[ci];
     std::vector<ChunkDesc> tab;
     std::vector<int32_t> starts;
-    std::vector<Job *> finishing;
+    std::vector<Job *> finishing, members;
     int64_t items = 0, pairs = 0;
     const int64_t max_items = kc.max_items;
     // a step always gives every resident wave several work items (the last items of a
@@ -378,6 +449,7 @@ bool Server::issue_step(int ci)
         Batch &b = j->batch;
         const int64_t fbase = dry ? 0 : (int64_t)((j->region + j->off_batch + b.off_coords) / sizeof(float));
         const int64_t pb = dry ? 0 : (int64_t)((j->region + j->off_batch + b.off_partial) / sizeof(double));
+        members.push_back(j);
         while (j->next_chunk < b.chunks.size() && (pairs < step_pairs || items < min_items) && items < max_items) {
             const size_t c = j->next_chunk;
             const ChunkDesc &src = b.chunks[c];
@@ -489,9 +561,19 @@ bool Server::issue_step(int ci)
         e = hipEventRecord(st.ev, sm);
     if (e == hipSuccess)
         e = hipEventRecord(kc.last_ev[slot], sm);
+    if (e == hipSuccess)
+        e = hipLaunchHostFunc(sm, host_wake, this);
     if (e != hipSuccess) {
-        for (Job *j : finishing)
-            fail_job(j, TE_ERR_DEVICE, hipGetErrorString(e));
+        // every job with blocks in this step lacks some partial sums: it fails, and is
+        // released once the class's streams (its earlier steps) have drained
+        const char *msg = hipGetErrorString(e);
+        drain_streams(&kc);
+        st.finishing.clear();
+        for (Job *j : members) {
+            fail_job(j, TE_ERR_DEVICE, msg);
+            j->all_scheduled = true;
+            st.finishing.push_back(j->id);
+        }
         if (st.ev)
             hipEventDestroy(st.ev);
         st.ev = nullptr;
@@ -549,7 +631,8 @@ void Server::poll_steps()
         }
         for (uint64_t id : st.finishing) {
             auto jt = jobs.find(id);
-            if (jt != jobs.end() && jt->second->state != CANCELLED) {
+            if (jt != jobs.end() && jt->second->state != CANCELLED && jt->second->state != DONE &&
+                jt->second->footprint != 0) {
                 Job *j = jt->second.get();
                 // the result copy was recorded before the step's event on the same stream
                 if (!dry && j->done_ev && j->state != FAILED)
@@ -601,11 +684,10 @@ void Server::loop()
         if (!busy && !issued) {
             if (stopping && resident.empty() && queue.empty())
                 break;
-            cv_work.wait_for(lk, std::chrono::milliseconds(2));
+            sleep_until_woken(lk, 50);
         } else if (!issued) {
-            lk.unlock();
-            std::this_thread::sleep_for(std::chrono::microseconds(dry ? 0 : 50));
-            lk.lock();
+            // device work in flight: its completion wakes the thread (the timeout is a backstop)
+            sleep_until_woken(lk, dry ? 1 : 10);
         }
     }
 }
@@ -623,6 +705,8 @@ te_status Server::start()
         dev.n_cu = 256;
     }
     alloc.init(arena_bytes);
+    if (const char *f = std::getenv("TE_SERVE_FAULT_STAGING"))
+        fault_staging = std::atoll(f);
     thr = std::thread([this] { loop(); });
     return TE_OK;
 }
@@ -677,16 +761,15 @@ te_status te_serve_submit(te_server srv, const te_problem *problem, const float 
         return st;
     j->plan.reset(pl);
     const Plan &P = pl->impl;
-    if (P.p.n_surrogates > 0 && !perms)
-        return fail(TE_ERR_INVALID, "n_surrogates > 0 needs perms");
+    const bool caller_perms = P.p.n_surrogates > 0 && perms != nullptr;
     j->batch = P.full;
-    j->footprint = job_footprint(P, &j->batch, &j->off_x, &j->off_y, &j->off_perm, &j->off_batch);
+    j->footprint = job_footprint(P, caller_perms, &j->batch, &j->off_x, &j->off_y, &j->off_perm, &j->off_batch);
     if (j->footprint > S.alloc.size)
         return fail(TE_ERR_NOMEM, "job needs %zu bytes, the arena holds %zu", j->footprint, S.alloc.size);
     // stage the inputs in pinned memory now, on the submitting thread, so the
     // server's uploads are asynchronous copies
     j->n_series = (size_t)P.p.n_pairs * P.p.n_trials * P.p.n_samples;
-    j->n_perm = P.p.n_surrogates > 0 ? (size_t)P.p.n_pairs * P.p.n_points * P.p.n_surrogates * P.p.n_trials : 0;
+    j->n_perm = caller_perms ? (size_t)P.p.n_pairs * P.p.n_points * P.p.n_surrogates * P.p.n_trials : 0;
     j->hin_y = align_up(sizeof(float) * j->n_series, 256);
     j->hin_perm = j->hin_y + align_up(sizeof(float) * j->n_series, 256);
     j->hin_bytes = j->hin_perm + sizeof(int32_t) * j->n_perm;
@@ -721,7 +804,7 @@ te_status te_serve_submit(te_server srv, const te_problem *problem, const float 
     *ticket = j->id;
     S.queue.push_back(j.get());
     S.jobs[j->id] = std::move(j);
-    S.cv_work.notify_all();
+    S.wake_up();
     return TE_OK;
 }
 
@@ -787,7 +870,7 @@ te_status te_serve_resume(te_server srv)
     Server &S = srv->impl;
     std::lock_guard<std::mutex> lk(S.mu);
     S.held = false;
-    S.cv_work.notify_all();
+    S.wake_up();
     return TE_OK;
 }
 
@@ -833,7 +916,7 @@ te_status te_serve_close(te_server srv)
             S.cancelled++;
         }
         S.queue.clear();
-        S.cv_work.notify_all();
+        S.wake_up();
         S.cv_done.notify_all();
     }
     if (S.thr.joinable())

@@ -284,8 +284,6 @@ te_status te_plan_autotune(te_plan plan, const float *x, const float *y, const i
     if (!plan || !x || !y || !ws_)
         return fail(TE_ERR_INVALID, "null argument");
     const Plan &P = plan->impl;
-    if (P.p.n_surrogates > 0 && !perms)
-        return fail(TE_ERR_INVALID, "n_surrogates > 0 needs perms");
     te_status s = P.ensure_device();
     if (s != TE_OK)
         return s;

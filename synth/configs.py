@@ -42,6 +42,7 @@ class Workload:
     perms: np.ndarray | None = None   # int32 [P, C, S, R] or None when S == 0
     meta: dict = field(default_factory=dict)
     cond_source: int = 0          # 1: condition on the current source sample x_t as well
+    perm_seed: int = 0            # seed of make_perms that drew ``perms`` (the library draws the same)
 
     @property
     def n_pairs(self) -> int:
@@ -108,7 +109,8 @@ def linear_pair(R=100, T=100, d=2, window=20, start=80, coupling=0.4, seed_offse
                  trials=np.array([R], np.int32), n_surrogates=n_surrogates,
                  meta=dict(seed=seed, coupling=coupling))
     if n_surrogates:
-        w.perms = make_perms(seed, 1, w.trials, n_surrogates, R)
+        w.perm_seed = int(seed)
+        w.perms = make_perms(w.perm_seed, 1, w.trials, n_surrogates, R)
     return w
 
 
@@ -129,7 +131,8 @@ def nonlinear_ensemble(R=500, T=300, n_points=100, window=10, k=4, n_surrogates=
                  trials=np.full(n_points, R, np.int32), n_surrogates=n_surrogates,
                  meta=dict(seed=seed))
     if n_surrogates:
-        w.perms = make_perms(seed, 1, w.trials, n_surrogates, R)
+        w.perm_seed = int(seed)
+        w.perms = make_perms(w.perm_seed, 1, w.trials, n_surrogates, R)
     return w
 
 
@@ -152,7 +155,8 @@ def uneven_surrogates(R=5000, T=400, n_points=60, n_surrogates=200, n_lo=1000, n
     w = Workload(name=name, x=x[None], y=y[None], d_y=3, d_x=3, tau=1, u=1, k=k,
                  window_start=starts, window_len=wl, trials=rc, n_surrogates=n_surrogates,
                  meta=dict(seed=seed))
-    w.perms = make_perms(seed, 1, rc, n_surrogates, R)
+    w.perm_seed = int(seed)
+    w.perms = make_perms(w.perm_seed, 1, rc, n_surrogates, R)
     return w
 
 
@@ -176,7 +180,8 @@ def meg_like(n_pairs=16, R=120, T=1200, n_points=40, window=20, n_surrogates=100
                  window_start=starts, window_len=np.full(n_points, window, np.int32),
                  trials=np.full(n_points, R, np.int32), n_surrogates=n_surrogates,
                  meta=dict(seeds=seeds, on=on, off=off))
-    w.perms = make_perms(seeds[0], n_pairs, w.trials, n_surrogates, R)
+    w.perm_seed = int(seeds[0])
+    w.perms = make_perms(w.perm_seed, n_pairs, w.trials, n_surrogates, R)
     return w
 
 
@@ -195,7 +200,8 @@ def generic(seed_ids, *, n_pairs=1, R=40, T=60, d_y=2, d_x=2, tau=1, u=1, k=4, s
                  window_start=np.array(starts, np.int32), window_len=wl, trials=tr,
                  n_surrogates=n_surrogates)
     if n_surrogates:
-        w.perms = make_perms(int(derive_key(*seed_ids) % np.uint64(1 << 31)), n_pairs, tr, n_surrogates, R)
+        w.perm_seed = int(int(derive_key(*seed_ids) % np.uint64(1 << 31)))
+        w.perms = make_perms(w.perm_seed, n_pairs, tr, n_surrogates, R)
     return w
 
 
@@ -219,7 +225,8 @@ def ar_scenarios(scenario=1, R=50, T=3000, window=300, n_surrogates=500, d_y=2, 
                  meta=dict(seed=seed, scenario=scenario, u_values=list(range(1, u_max + 1)),
                            directions=["X->Y", "Y->X"]))
     if n_surrogates:
-        w.perms = make_perms(seed, 2, w.trials, n_surrogates, R)
+        w.perm_seed = int(seed)
+        w.perms = make_perms(w.perm_seed, 2, w.trials, n_surrogates, R)
     return w
 
 
@@ -240,7 +247,8 @@ def ar_robustness(R=100, T=3000, window=300, start=1100, trials=(2, 7, 17, 34, 1
                  meta=dict(seed=seed, scenario=1, u_values=list(range(1, 21)), directions=["X->Y"],
                            points=[int(r) * window for r in trials]))
     if n_surrogates:
-        w.perms = make_perms(seed, 1, w.trials, n_surrogates, R)
+        w.perm_seed = int(seed)
+        w.perms = make_perms(w.perm_seed, 1, w.trials, n_surrogates, R)
     return w
 
 
@@ -271,8 +279,9 @@ def served_jobs(n_jobs=2000, rate=200.0, n_lo=1000, n_hi=100000, s_max=500, seed
     return jobs
 
 
-def job_workload(job: dict, k: int = 4) -> Workload:
-    """The series of one served job: linear AR pair, u = 1, tau = 1, one window at the end."""
+def job_workload(job: dict, k: int = 4, with_perms: bool = True) -> Workload:
+    """The series of one served job: linear AR pair, u = 1, tau = 1, one window at the end.
+    with_perms=False leaves ``perms`` unset (the library draws the same ones from perm_seed)."""
     d, W, R, S = job["d"], job["W"], job["R"], job["S"]
     h = history(d, d, 1, 1)
     T = h + W
@@ -281,5 +290,7 @@ def job_workload(job: dict, k: int = 4) -> Workload:
     w = Workload(name=f"job{job['id']}", x=x[None], y=y[None], d_y=d, d_x=d, tau=1, u=1, k=k,
                  window_start=np.array([h], np.int32), window_len=np.array([W], np.int32),
                  trials=np.array([R], np.int32), n_surrogates=S, meta=dict(job=job))
-    w.perms = make_perms(seed, 1, w.trials, S, R)
+    w.perm_seed = int(seed)
+    if with_perms:
+        w.perms = make_perms(w.perm_seed, 1, w.trials, S, R)
     return w

@@ -400,7 +400,7 @@ def test_work_counters_and_pruning(te):
     wl = synth.nonlinear_ensemble(R=300, T=60, n_points=4, window=10)
     x, y, _ = dev(wl)
     plan = te.Plan.from_workload(wl)
-    te.profile_enable(True)
+    te.profile_enable(True, work=True)
     te.profile_work(reset=True)
     plan.surrogates(x, y)
     w1, w2 = te.profile_work(reset=True)
@@ -581,3 +581,19 @@ def test_meg_like_full_size_sampled(te):
     rng_picks = np.floor(uniform01(derive_key(4242), 24) * np.array([16, 40, 101] * 8)).astype(int).reshape(8, 3)
     picks = [tuple(int(v) for v in r) for r in rng_picks] + [(0, 0, 0), (15, 39, 100)]
     _sampled_compare(wl, got, picks)
+
+
+@pytest.mark.parametrize("cond", [0, 1])
+def test_plain_per_chunk_path_equals_batched(te, cond):
+    """te_estimate_each (every chunk on its own: embed, search, reduce) gives the batched
+    path's estimates and p-values bit for bit, with given and with drawn permutations."""
+    wl = synth.uneven_surrogates(R=200, T=60, n_points=4, n_surrogates=6, n_lo=100, n_hi=2500)
+    wl.cond_source = cond
+    x, y, perms = dev(wl)
+    plan = te.Plan.from_workload(wl)
+    ref = plan.surrogates(x, y, perms)
+    say("plain per chunk, cond", cond, wl.chunk_sizes())
+    for got in (plan.estimate_each(x, y, perms), plan.estimate_each(x, y, None)):
+        for u, v in zip(ref, got):
+            np.testing.assert_array_equal(u, v)
+    np.testing.assert_array_equal(plan.estimate(x, y), ref[0])

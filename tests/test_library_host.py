@@ -145,9 +145,25 @@ def test_async_rejects_missing_arguments_without_gpu():
         (null, dummy, dummy, dummy, dummy, dummy),   # no plan
         (p._h, null, dummy, dummy, dummy, dummy),    # no x
         (p._h, dummy, dummy, dummy, dummy, null),    # no out
-        (p._h, dummy, dummy, null, dummy, dummy),    # surrogates without perms
     ]
     for plan, x, y, perms, ws, out in cases:
         st = L.te_surrogates_async(plan, x, y, perms, ws, 1 << 20, null, out)
         assert st == 1, st
         assert L.te_last_error() is not None
+
+
+def test_drawn_permutation_sizes_and_checks_without_gpu():
+    """Surrogates without caller permutations are drawn from the plan's seed; the
+    permutation export sizes its workspace and checks its arguments on the host."""
+    from paper_1401_4068_amd import _lib
+    _lib_or_build()
+    L = _lib.lib()
+    p = _plan(n_surrogates=3, window_start=[10, 20], window_len=[10, 5], trials=[20, 12], seed=7)
+    nb = L.te_plan_permutations_workspace_bytes(p._h)
+    assert nb >= 6 * 40                               # one 40-byte row descriptor per surrogate chunk
+    assert L.te_plan_permutations_workspace_bytes(ctypes.c_void_p(0)) == 0
+    null = ctypes.c_void_p(0)
+    assert L.te_plan_permutations(p._h, null, nb, null, ctypes.c_void_p(1 << 20)) == 1
+    assert L.te_plan_permutations(p._h, ctypes.c_void_p(1 << 20), nb - 1, null, ctypes.c_void_p(1 << 20)) == 2
+    q = _plan(n_surrogates=0)
+    assert L.te_plan_permutations(q._h, ctypes.c_void_p(1 << 20), 256, null, ctypes.c_void_p(1 << 20)) == 0

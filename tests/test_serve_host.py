@@ -91,3 +91,22 @@ def test_close_cancels_queued_jobs(te):
     srv = te.Server(arena_bytes=1 << 20, max_slots=1, dry_run=True, hold=True)
     t = srv.submit(_job(6))
     srv.close()
+
+
+def test_failed_staging_releases_the_job_and_the_queue_moves_on(te, monkeypatch):
+    """An admission whose pinned staging fails (injected) fails only its own job, with
+    TE_ERR_NOMEM; its arena region is returned and the jobs behind it complete."""
+    monkeypatch.setenv("TE_SERVE_FAULT_STAGING", "2")
+    srv = te.Server(arena_bytes=64 << 20, max_slots=2, dry_run=True)
+    tickets = [srv.submit(_job(i)) for i in range(5)]
+    outcomes = []
+    for t in tickets:
+        try:
+            srv.wait(t, timeout_s=30)
+            outcomes.append("ok")
+        except te.TEError as e:
+            outcomes.append(e.status)
+    st = srv.stats()
+    srv.close()
+    assert outcomes.count(2) == 1 and outcomes.count("ok") == 4, outcomes
+    assert st["completed"] == 4 and st["failed"] == 1 and st["resident"] == 0 and st["queued"] == 0

@@ -146,10 +146,14 @@ def test_drawn_surrogates_equal_explicit_ones_and_the_oracle(te):
         for u, v in zip(a, g):
             np.testing.assert_array_equal(u, v)
         torch.cuda.synchronize()
-    # delay scan and the server
-    u_values = [1, 2, 3]
-    d1 = plan.delay_scan(x, y, u_values, perms)
-    d2 = plan.delay_scan(x, y, u_values, None)
+    # delay scan (a workload with history for every delay) and the server
+    ws_ = synth.generic((97,), n_pairs=2, R=120, T=80, d_y=2, d_x=2, u=3, starts=(20, 35), windows=(10, 7),
+                        trials=(120, 80), n_surrogates=5, coupling=0.6)
+    xs, ys, ps = dev(ws_)
+    splan = te.Plan.from_workload(ws_)
+    u_values = [1, 2, 3, 4]
+    d1 = splan.delay_scan(xs, ys, u_values, ps)
+    d2 = splan.delay_scan(xs, ys, u_values, None)
     for u, v in zip(d1, d2):
         np.testing.assert_array_equal(u, v)
     srv = te.Server(arena_bytes=512 << 20, max_slots=4)

@@ -1,4 +1,10 @@
-"""Build libte.so (HIP kernels for gfx950 + host runtime) in-tree with hipcc."""
+"""Build libte.so (HIP kernels for gfx950 + host runtime) in-tree with hipcc.
+
+`python -m paper_1401_4068_amd.build --sanitize address|thread` builds a copy of the
+library whose host code is instrumented with AddressSanitizer or ThreadSanitizer
+(device code is compiled as usual), as _build/<kind>/libte_<kind>.so, for CPU runs of
+the host-logic tests with the sanitizer runtime preloaded (commands in the design notes).
+"""
 from __future__ import annotations
 
 import glob
@@ -18,11 +24,16 @@ ARCH = "gfx950"
 # Packed FP32 instructions are disabled for all device code.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + INCLUDE, "-I" + CSRC]
+# host-only instrumentation: each sanitizer flag applies to the host compilation alone
+SANITIZE = {
+    "address": ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer", "-g"],
+    "thread": ["-Xarch_host", "-fsanitize=thread", "-g"],
+}
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = ["hipcc", "--offload-arch=" + ARCH] + COMMON + DEVICE_FLAGS + ["-c", src, "-o", obj]
+def _compile(src: str, objdir: str, extra: list) -> str:
+    obj = os.path.join(objdir, os.path.basename(src) + ".o")
+    cmd = ["hipcc", "--offload-arch=" + ARCH] + COMMON + DEVICE_FLAGS + extra + ["-c", src, "-o", obj]
 
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -31,22 +42,30 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OBJ, exist_ok=True)
+def build(verbose: bool = False, sanitize: str = "") -> str:
+    extra = SANITIZE[sanitize] if sanitize else []
+    objdir = os.path.join(OBJ, sanitize) if sanitize else OBJ
+    out = os.path.join(objdir, "libte_%s.so" % sanitize) if sanitize else OUT
+    os.makedirs(objdir, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = OUT + ".tmp%d" % os.getpid()
+        objs = list(ex.map(lambda s: _compile(s, objdir, extra), srcs))
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
+    if sanitize:
+        cmd += ["-Xarch_host", "-fsanitize=" + sanitize, "-shared-libsan"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("link failed")
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
     if verbose:
-        print("built", OUT)
-    return OUT
+        print("built", out)
+    return out
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sanitize", choices=sorted(SANITIZE), default="")
+    build(verbose=True, sanitize=ap.parse_args().sanitize)

@@ -8,6 +8,7 @@ would exceed.
 """
 import math
 import sys
+import zlib
 
 import numpy as np
 import pytest
@@ -66,7 +67,7 @@ def _points(key, N, D, kind):
 def _knn_case(te, sizes, d_y, d_x, k, kind, seed=0):
     import torch
     D = 1 + d_y + d_x
-    chunks = [_points(derive_key(seed, n, D, k, hash(kind) & 0xFFFF), n, D, kind) for n in sizes]
+    chunks = [_points(derive_key(seed, n, D, k, zlib.crc32(kind.encode()) & 0xFFFF), n, D, kind) for n in sizes]
     off = np.zeros(len(sizes) + 1, np.int64)
     off[1:] = np.cumsum(sizes)
     stride = int(off[-1]) + 37            # coordinate stride larger than the point count

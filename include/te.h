@@ -245,6 +245,26 @@ te_status te_knn_counts(const float *pts, int64_t dim_stride, const int64_t *off
                         void *ws, size_t ws_bytes, void *hip_stream,
                         float *eps, int32_t *counts, double *te_out);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: te_knn_counts
+ * with its device scratch (tables, sorted copy, sort keys, partial sums, queue
+ * counters) in a static array of the library instead of a caller workspace.
+ * The array holds TE_NOALLOC_SCRATCH_BYTES per device; each device that runs
+ * the library's code holds its own copy until the process ends.
+ *   Arguments, layouts and results as te_knn_counts (identical bit for bit).
+ *   TE_ERR_NOMEM when te_knn_counts_workspace_bytes(n_chunks, offsets[n_chunks])
+ *   exceeds TE_NOALLOC_SCRATCH_BYTES (up to about 590 000 points in all).
+ * The call allocates no device memory and no pinned host memory: tables go up
+ * and te_out comes down through ordinary host memory, and the stream is
+ * synchronised before the call returns.  Every call on one device uses the same
+ * array and leaves its contents behind (the queue counters are cleared at the
+ * start of each call): calls that overlap on one device, from several threads or
+ * streams, race and must be serialised by the caller. */
+#define TE_NOALLOC_SCRATCH_BYTES (32u << 20)
+te_status te_knn_counts_noalloc(const float *pts, int64_t dim_stride, const int64_t *offsets,
+                                int32_t n_chunks, int32_t d_y, int32_t d_x, int32_t k, void *hip_stream,
+                                float *eps, int32_t *counts, double *te_out);
+
 /* ------------------------------------------------------------------ serving
  * A server keeps admitted jobs resident in a caller-provided device arena and
  * batches their searches continuously: a server thread admits queued jobs in

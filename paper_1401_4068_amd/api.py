@@ -395,6 +395,29 @@ def knn_counts(pts, offsets, d_y, d_x, k, stream=None, ws=None, want_te=True):
     return eps[:total], cnt[:, :total], te
 
 
+def knn_counts_noalloc(pts, offsets, d_y, d_x, k, eps, counts, stream=None, want_te=True):
+    """te_knn_counts with the library's static device scratch (te_knn_counts_noalloc): the
+    call itself allocates no device memory.  eps (CUDA float32 [>= total]) and counts (CUDA
+    int32 [3, stride >= total], rows counts[s, :total]) are the caller's outputs; the counts
+    use the row stride total, so pass counts of shape [3, total].  Returns te float64 [C] or None."""
+    torch = _torch()
+    off = np.ascontiguousarray(offsets, np.int64)
+    C = off.shape[0] - 1
+    total = int(off[-1])
+    D = 1 + d_y + d_x
+    if pts.dim() != 2 or pts.shape[0] != D:
+        raise ValueError("pts must be [1 + d_y + d_x, stride]")
+    if eps.numel() < total or counts.dim() != 2 or counts.shape[0] != 3 or counts.shape[1] != total:
+        raise ValueError("eps must hold >= total points and counts must be [3, total]")
+    te = np.empty(C, np.float64) if want_te else None
+    sh, _ = _stream_handle(stream)
+    check(lib().te_knn_counts_noalloc(_dev_ptr(pts, torch.float32, "pts"), pts.shape[1],
+                                      off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), C, d_y, d_x, k, sh,
+                                      _dev_ptr(eps, torch.float32, "eps"), _dev_ptr(counts, torch.int32, "counts"),
+                                      _dp(te) if want_te else None))
+    return te
+
+
 def autotune(d_y, d_x, k, n_points, n_chunks=None, stream=None):
     """Time every search launch shape on synthetic chunks (te_autotune); the winner is
     used by plans created afterwards.  Returns the chosen shape and its time."""

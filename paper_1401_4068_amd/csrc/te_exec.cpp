@@ -487,7 +487,27 @@ te_status te_knn_counts(const float *pts, int64_t dim_stride, const int64_t *off
                         int32_t *counts, double *te_out)
 {
     clear_error();
-    if (!pts || !offsets || !ws_ || !eps || !counts)
+    if (!ws_)
+        return fail(TE_ERR_INVALID, "null argument");
+    return knn_counts_run(pts, dim_stride, offsets, n_chunks, d_y, d_x, k, static_cast<char *>(ws_), ws_bytes,
+                          (hipStream_t)hip_stream, eps, counts, te_out, true, "workspace");
+}
+
+}  // extern "C"
+
+namespace te {
+
+// Body of te_knn_counts and te_knn_counts_noalloc.  ws: device scratch of ws_bytes
+// (the caller's workspace, or the library's static scratch array).  pinned_staging:
+// upload the tables and download the estimates through the pinned staging pool
+// (which may allocate pinned host memory on first use); false: through ordinary
+// host memory, so the call allocates no device or pinned memory.  ws_name names the
+// scratch in the TE_ERR_NOMEM message.
+te_status knn_counts_run(const float *pts, int64_t dim_stride, const int64_t *offsets, int32_t n_chunks, int32_t d_y,
+                         int32_t d_x, int32_t k, char *ws, size_t ws_bytes, hipStream_t st, float *eps,
+                         int32_t *counts, double *te_out, bool pinned_staging, const char *ws_name)
+{
+    if (!pts || !offsets || !ws || !eps || !counts)
         return fail(TE_ERR_INVALID, "null argument");
     if (n_chunks < 1)
         return fail(TE_ERR_INVALID, "n_chunks must be >= 1");
@@ -562,7 +582,6 @@ te_status te_knn_counts(const float *pts, int64_t dim_stride, const int64_t *off
     if (s != TE_OK)
         return s;
     SearchConfig cfg = default_config(dev, d_y, d_x, k, total / n_chunks);
-    char *ws = static_cast<char *>(ws_);
     size_t o = 0;
     const size_t off_chunks = o;
     o = align_up(o + sizeof(ChunkDesc) * n_chunks, 16);
@@ -586,12 +605,19 @@ te_status te_knn_counts(const float *pts, int64_t dim_stride, const int64_t *off
     const size_t off_scratch = o;
     o = align_up(o + (sorted ? sizeof(uint64_t) * (size_t)n_scratch : 0), 256);
     if (ws_bytes < o)
-        return fail(TE_ERR_NOMEM, "workspace too small (%zu < %zu bytes)", ws_bytes, o);
-    hipStream_t st = (hipStream_t)hip_stream;
+        return fail(TE_ERR_NOMEM, "%s too small (%zu < %zu bytes)", ws_name, ws_bytes, o);
     const size_t out_off = align_up(tbytes, 256);
-    char *stg = static_cast<char *>(g_knn_pool.take(out_off + sizeof(double) * n_chunks + 64));
-    if (!stg)
-        return fail(TE_ERR_NOMEM, "pinned staging allocation failed");
+    const size_t stg_bytes = out_off + sizeof(double) * n_chunks + 64;
+    std::vector<char> host_stage;
+    char *stg;
+    if (pinned_staging) {
+        stg = static_cast<char *>(g_knn_pool.take(stg_bytes));
+        if (!stg)
+            return fail(TE_ERR_NOMEM, "pinned staging allocation failed");
+    } else {
+        host_stage.resize(stg_bytes);
+        stg = host_stage.data();
+    }
     std::memcpy(stg + off_chunks, sorted_chunks.data(), sizeof(ChunkDesc) * n_chunks);
     std::memcpy(stg + off_items, starts.data(), sizeof(int32_t) * n_chunks);
     std::memcpy(stg + off_sorts, sorts.data(), sizeof(SortTask) * n_chunks);
@@ -634,10 +660,11 @@ te_status te_knn_counts(const float *pts, int64_t dim_stride, const int64_t *off
         e = hipStreamSynchronize(st);
     if (e == hipSuccess && te_out)
         std::memcpy(te_out, stg + out_off, sizeof(double) * n_chunks);
-    g_knn_pool.give(stg);
+    if (pinned_staging)
+        g_knn_pool.give(stg);
     if (e != hipSuccess)
         return hip_fail(e, "te_knn_counts");
     return TE_OK;
 }
 
-}  // extern "C"
+}  // namespace te

@@ -23,6 +23,9 @@ int size_bucket(int64_t n);
 bool sorting_enabled();
 int sort_npad(int n);
 void queue_bounds(const std::vector<ChunkDesc> &pieces, int64_t n_items, std::vector<int32_t> *part_start);
+te_status knn_counts_run(const float *pts, int64_t dim_stride, const int64_t *offsets, int32_t n_chunks, int32_t d_y,
+                         int32_t d_x, int32_t k, char *ws, size_t ws_bytes, hipStream_t st, float *eps,
+                         int32_t *counts, double *te_out, bool pinned_staging, const char *ws_name);
 
 // A set of chunks laid out in one device workspace, with the host copy of its
 // tables.  Chunks are stored in schedule (longest-first) order.

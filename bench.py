@@ -50,17 +50,27 @@ def ops_per_pair(D: int) -> int:
     return 4 * D + 2
 
 
-def min_instr_per_pair(D: int) -> int:
-    """The fewest FP32 VALU instructions that carry a pair's 4D + 2 ops without packed math: a
-    subtraction or a compare is one op per instruction, two maxes fold into one 3-input v_max3
-    (abs is a free source modifier): 2D subtractions + 2 floor(D/2) v_max3 + 4 compares."""
-    return 2 * D + 2 * (D // 2) + 4
+def executed_ops(DT: int, DX: int, w):
+    """FP32 ops the search executed, by kind, from its four work counters w = (pass-1 and pass-2
+    (reference, candidate, chunk) triples, pass-1 and pass-2 (reference, candidate) pairs whose
+    target coordinates were compared once for a set of chunks).  Per shared pair: DT subtractions
+    and DT - 1 maxes in either pass (pass 2: the target-past max and max(d_T, d_P)); per triple,
+    pass 1: DX subtractions, DX maxes (source block, then the joint max), 1 compare; pass 2: DX
+    subtractions, DX maxes (source block, then max(d_P, d_S)), 3 compares.  Without sets (shared
+    pairs = triples) this is 2D per pass-1 pair and 2D + 2 per pass-2 pair."""
+    p1, p2, s1, s2 = (float(v) for v in w)
+    sub = (s1 + s2) * DT + (p1 + p2) * DX
+    mx = (s1 + s2) * (DT - 1) + (p1 + p2) * DX
+    cmp = p1 + 3 * p2
+    return sub, mx, cmp
 
 
-def valu_ceiling(D: int) -> float:
-    """FP32 VALU roofline of this op mix (T ops/s): 78.6e12 lane-instructions/s times the ops
-    per instruction of the fewest-instruction form (30 / 24 at D = 7: 98.3 T)."""
-    return FP32_LANE_INSTR_PER_S * ops_per_pair(D) / min_instr_per_pair(D) / 1e12
+def valu_ceiling(sub: float, mx: float, cmp: float) -> float:
+    """FP32 VALU roofline of an op mix (T ops/s): 78.6e12 lane-instructions/s times the ops per
+    instruction of its fewest-instruction form without packed math -- a subtraction or a compare
+    is one op per instruction, two maxes fold into one 3-input v_max3 (abs is a free source
+    modifier).  Without sets at D = 7: 30 ops in 24 instructions, 98.3 T."""
+    return FP32_LANE_INSTR_PER_S * (sub + mx + cmp) / (sub + mx / 2 + cmp) / 1e12
 
 
 # HBM bytes per search launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs, scaled by a plain 256 MiB
@@ -190,28 +200,32 @@ def make_workload(name):
     raise SystemExit("unknown workload " + name)
 
 
-def roofline_record(wl, wname, k_ms, k_n, w1, w2, work_launches, slots, pairs_per_pass_step):
-    """The search kernel on the FP32 VALU roofline.  achieved = algorithmic ops of the pairs one
-    launch evaluates (2D per pass-1 pair, 2D + 2 per pass-2 pair; device counters of an untimed
-    step) / the average launch duration of the timed steps (HIP events on the launch stream)."""
+def roofline_record(wl, wname, k_ms, k_n, w, work_launches, slots, pairs_per_pass_step):
+    """The search kernel on the FP32 VALU roofline.  achieved = FP32 ops the launch executed (device
+    work counters of an untimed step, see executed_ops) / the average launch duration of the timed
+    steps (HIP events on the launch stream); peak = the VALU ceiling of that op mix."""
     D = wl.dim
+    DT, DX = 1 + wl.d_y + wl.cond_source, wl.d_x
     avg_s = k_ms / k_n / 1e3
-    p1, p2 = w1 / work_launches, w2 / work_launches
-    ops = p1 * 2 * D + p2 * (2 * D + 2)
+    w = [v / work_launches for v in w]
+    sub, mx, cmp = executed_ops(DT, DX, w)
+    ops = sub + mx + cmp
     method_ops = pairs_per_pass_step * ops_per_pair(D)
     achieved = ops / avg_s / 1e12
     method_tops = method_ops / avg_s / 1e12
-    ceil = valu_ceiling(D)
+    ceil = valu_ceiling(sub, mx, cmp)
     return dict(
         bound="alu", achieved=round(achieved, 3), peak=round(ceil, 3), unit="TFLOP/s",
         frac=round(achieved / ceil, 4), traffic=kernel_traffic(wname),
-        peak_derivation="78.64e12 FP32 lane-instr/s (256 CU x 4 SIMD x 32 lanes x 2.4 GHz) x %d ops per %d "
-                        "instructions (2D sub + 2 floor(D/2) v_max3 + 4 cmp, D = %d; no packed FP32)"
-                        % (ops_per_pair(D), min_instr_per_pair(D), D),
-        kernel="search_kernel<%d,%d,k=%d,slots=%d,sorted>" % (wl.d_y + wl.cond_source, wl.d_x, wl.k, slots),
+        peak_derivation="78.64e12 FP32 lane-instr/s (256 CU x 4 SIMD x 32 lanes x 2.4 GHz) x executed ops per "
+                        "instruction of their fewest-instruction form (%.3g sub + %.3g max + %.3g cmp per launch; "
+                        "sub and cmp one op per instruction, two maxes per v_max3; no packed FP32)" % (sub, mx, cmp),
+        kernel="search_%s<%d,%d,k=%d,slots=%d,sorted>" % ("sets_kernel" if w[2] < w[0] else "kernel", DT - 1, DX,
+                                                           wl.k, slots),
         kernel_src=kernel_sha(), avg_launch_ms=round(avg_s * 1e3, 4), launches=k_n,
-        pairs_evaluated_per_launch=[int(p1), int(p2)], ops_per_launch=int(ops),
-        method_pairs_per_launch=int(pairs_per_pass_step), method_equivalent_tops=round(method_tops, 3),
+        pairs_evaluated_per_launch=[int(w[0]), int(w[1])], shared_pairs_per_launch=[int(w[2]), int(w[3])],
+        ops_per_launch=int(ops), method_pairs_per_launch=int(pairs_per_pass_step),
+        method_equivalent_tops=round(method_tops, 3),
         frac_method_equivalent=round(method_tops / ceil, 4),
         frac_of_headline_157_3=round(achieved / PEAK_FP32_HEADLINE, 4),
         method_frac_of_headline_157_3=round(method_tops / PEAK_FP32_HEADLINE, 4))
@@ -274,9 +288,9 @@ def batched_record(args, wl, wname):
     print("timed %d steps: %.4f s per step" % (args.steps, dt / args.steps), file=sys.stderr, flush=True)
     # one untimed step with the device counters of evaluated pairs
     te.profile_enable(False, work=True)
-    te.profile_work(reset=True)
+    te.profile_work_all(reset=True)
     step_async() if pipelined else step()
-    w1, w2 = te.profile_work(reset=True)
+    work = te.profile_work_all(reset=True)
     te.profile_enable(False)
     # results of the last queued step against a synchronous call with the input module's
     # permutations (bit for bit), and the latency of synchronous calls (a step and its host round trip)
@@ -302,7 +316,7 @@ def batched_record(args, wl, wname):
     slots = tuned["slots"] if tuned else 4
     roof = None
     if k_n > 0:
-        roof = roofline_record(wl, wname, k_ms, k_n, w1, w2, 1, slots, pairs_per_pass * args.steps / k_n)
+        roof = roofline_record(wl, wname, k_ms, k_n, work, 1, slots, pairs_per_pass * args.steps / k_n)
 
     # plain per-time-point paths on the same work
     plain_rec = None
@@ -452,14 +466,14 @@ def scan_record(args, scenario):
     k_ms, k_n = te.profile_read(reset=True)
     # one untimed step with the device counters of evaluated pairs (two launches)
     te.profile_enable(False, work=True)
-    te.profile_work(reset=True)
+    te.profile_work_all(reset=True)
     step()
-    w1, w2 = te.profile_work(reset=True)
+    work = te.profile_work_all(reset=True)
     te.profile_enable(False)
     roof = None
     if k_n > 0:
         # two search launches per step (all delays; the chosen delay's test): their mean
-        roof = roofline_record(wl, "ar_scan", k_ms, k_n, w1, w2, 2, tuned["slots"] if tuned else 4,
+        roof = roofline_record(wl, "ar_scan", k_ms, k_n, work, 2, tuned["slots"] if tuned else 4,
                                pairs_per_step / 2)
     te_scan, u_best, _, pv = out
     findings = []

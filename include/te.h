@@ -367,6 +367,13 @@ te_status te_profile_read(double *search_ms, int64_t *launches, int32_t reset);
  * (counts); with sorted search spaces these are below the method's N(N-1) per
  * pass.  Synchronises the device. */
 te_status te_profile_work(int64_t *pass1_pairs, int64_t *pass2_pairs, int32_t reset);
+/* All four counters: counts[0], counts[1] as te_profile_work (one pair per
+ * chunk); counts[2], counts[3] the (reference, candidate) pairs of pass 1 and
+ * pass 2 whose target coordinates (y_t', Y_past) were compared: the window
+ * chunks searched together as one set (originals, surrogates or delays of one
+ * window) share those comparisons, so these are below counts[0], counts[1]
+ * when sets are used, and equal to them otherwise.  counts: host int64 [4]. */
+te_status te_profile_work_all(int64_t *counts, int32_t reset);
 
 #ifdef __cplusplus
 }

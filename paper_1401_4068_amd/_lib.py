@@ -65,6 +65,7 @@ SIGNATURES = {
     "te_profile_enable": ([_i32], _st),
     "te_profile_read": ([_dp, ctypes.POINTER(_i64), _i32], _st),
     "te_profile_work": ([ctypes.POINTER(_i64), ctypes.POINTER(_i64), _i32], _st),
+    "te_profile_work_all": ([ctypes.POINTER(_i64), _i32], _st),
     "te_serve_open": ([_vp, _sz, _i32, _i32, _i64, _i32, ctypes.POINTER(_vp)], _st),
     "te_serve_submit": ([_vp, ctypes.POINTER(Problem), _vp, _vp, _vp, ctypes.POINTER(ctypes.c_uint64)], _st),
     "te_serve_wait": ([_vp, ctypes.c_uint64, _i64, _dp, _dp, _dp], _st),

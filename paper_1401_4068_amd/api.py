@@ -471,5 +471,13 @@ def profile_work(reset: bool = False):
     return a.value, b.value
 
 
+def profile_work_all(reset: bool = False):
+    """(pass-1 pairs, pass-2 pairs, pass-1 shared pairs, pass-2 shared pairs): the first two
+    count a pair once per chunk, the last two once per set of chunks searched together."""
+    w = (ctypes.c_int64 * 4)()
+    check(lib().te_profile_work_all(w, int(bool(reset))))
+    return tuple(int(v) for v in w)
+
+
 def version() -> str:
     return lib().te_version().decode()

@@ -133,19 +133,39 @@ void Batch::finish_layout()
     std::vector<ChunkDesc> sorted;
     sorted.reserve(chunks.size());
     item_start.clear();
+    set_first.clear();
     n_items = 0;
+    n_partials = 0;
+    std::vector<ChunkDesc> leaders;       // first chunk of each set, n scaled by the set's size (queue costs)
     for (int c : order) {
         ChunkDesc d = chunks[c];
-        d.item0 = (int32_t)n_items;
+        const int64_t nb = (d.n + kWave - 1) / kWave;
+        // a new work unit: every chunk without sets; with sets, when the previous set is
+        // full or belongs to another window (the stable LPT order keeps a window's chunks together)
+        const bool start = !use_sets || set_first.empty() || (int)sorted.size() - set_first.back() >= kSetVariants ||
+                           sorted.back().tp != d.tp || sorted.back().n != d.n;
+        if (start) {
+            d.item0 = (int32_t)n_items;
+            item_start.push_back(d.item0);
+            if (use_sets) {
+                set_first.push_back((int32_t)sorted.size());
+                leaders.push_back(d);
+            }
+            n_items += nb;
+        } else {
+            d.item0 = sorted.back().item0;
+            leaders.back().n += d.n;
+        }
         d.block0 = 0;
-        d.pbase = n_items;
-        n_items += (d.n + kWave - 1) / kWave;
-        item_start.push_back(d.item0);
+        d.pbase = n_partials;
+        n_partials += nb;
         sorted.push_back(d);
     }
     chunks.swap(sorted);
+    if (use_sets)
+        set_first.push_back((int32_t)chunks.size());
 
-    queue_bounds(chunks, n_items, &part_start);
+    queue_bounds(use_sets ? leaders : chunks, n_items, &part_start);
 
     size_t o = 0;
     off_coords = o;
@@ -163,9 +183,11 @@ void Batch::finish_layout()
     o = align_up(o + sizeof(SortTask) * sorts.size(), 16);
     off_parts = o;
     o = align_up(o + sizeof(int32_t) * part_start.size(), 16);
+    off_sets = o;
+    o = align_up(o + sizeof(int32_t) * set_first.size(), 16);
     tables_bytes = o - off_tables;
     off_partial = align_up(o, 256);
-    o = off_partial + sizeof(double) * (size_t)std::max<int64_t>(n_items, 1);
+    o = off_partial + sizeof(double) * (size_t)std::max<int64_t>(n_partials, 1);
     // results, p-values and a copy of the error word back to back: one download
     off_results = align_up(o, 256);
     o = off_results + sizeof(double) * (size_t)std::max(n_results, 1);
@@ -198,6 +220,8 @@ void Batch::finish_layout()
     if (!sorts.empty())
         std::memcpy(host_tables.data() + (off_sorts - off_tables), sorts.data(), sizeof(SortTask) * sorts.size());
     std::memcpy(host_tables.data() + (off_parts - off_tables), part_start.data(), sizeof(int32_t) * part_start.size());
+    if (!set_first.empty())
+        std::memcpy(host_tables.data() + (off_sets - off_tables), set_first.data(), sizeof(int32_t) * set_first.size());
 }
 
 bool sorting_enabled()
@@ -230,6 +254,7 @@ te_status Plan::build_group_batch(const std::vector<int> &groups, int n_surr, Ba
     // that share one (y_t', Y_past) block.
     b->n_groups = (int)groups.size();
     b->n_surr = n_surr;
+    b->use_sets = opt.allow_sets && !opt.local_outputs && n_surr >= 1 && sets_eligible();
     b->n_results = b->n_groups * (n_surr + 1);
     b->groups = groups;
     int64_t fl = 0;
@@ -391,6 +416,24 @@ int Plan::grid_waves(int64_t n_items) const
     return (int)std::max<int64_t>(1, std::min<int64_t>(full, n_items));
 }
 
+bool Plan::sets_eligible() const
+{
+    const char *v = std::getenv("TE_NO_SETS");
+    if (v && *v && *v != '0')
+        return false;
+    return sorted && p.cond_source == 0 && search_sets_supported(dy_eff(), p.d_x, p.k);
+}
+
+SearchConfig Plan::batch_config(const Batch &b) const
+{
+    SearchConfig c = cfg;
+    if (b.use_sets) {
+        const int occ = search_sets_occupancy(dy_eff(), p.d_x, c.slots, c.waves_per_wg);
+        c.wg_per_cu = std::max(1, std::min(c.wg_per_cu, occ));
+    }
+    return c;
+}
+
 // Enqueue one batch: upload tables, embed, search, reduce, p-values, copy results
 // into the pinned staging block `stage` (results, p-values, error word).
 te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, const int32_t *perms, char *ws,
@@ -437,7 +480,8 @@ te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, co
     a.base = base;
     a.chunks = reinterpret_cast<const ChunkDesc *>(ws + b.off_chunks);
     a.item_start = reinterpret_cast<const int32_t *>(ws + b.off_items);
-    a.n_chunks = (int32_t)b.chunks.size();
+    a.n_chunks = (int32_t)(b.use_sets ? b.set_first.size() - 1 : b.chunks.size());
+    a.set_first = b.use_sets ? reinterpret_cast<const int32_t *>(ws + b.off_sets) : nullptr;
     a.n_items = (int32_t)b.n_items;
     a.k = p.k;
     a.counter = qctr;
@@ -450,13 +494,16 @@ te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, co
     a.lte_out = lte_out;
     a.perm_base = sigma;
     a.sorted = sorted ? 1 : 0;
-    if ((e = launch_search_timed(a, dy_eff(), p.d_x, cfg, grid_waves(b.n_items), st)) != hipSuccess)
+    const SearchConfig bc = batch_config(b);
+    const int64_t full_grid = (int64_t)dev.n_cu * bc.wg_per_cu * bc.waves_per_wg;
+    if ((e = launch_search_timed(a, dy_eff(), p.d_x, bc,
+                                 (int)std::max<int64_t>(1, std::min<int64_t>(full_grid, b.n_items)), st)) != hipSuccess)
         return hip_fail(e, "search launch");
     double *res = reinterpret_cast<double *>(ws + b.off_results);
     double *pv = reinterpret_cast<double *>(ws + b.off_pv);
     int32_t *err_out = reinterpret_cast<int32_t *>(ws + b.off_errout);
-    if ((e = launch_reduce(a.chunks, a.n_chunks, a.partial, p.k, ctr + 1, res, st, b.n_groups, b.n_surr, pv, ctr + 2,
-                           err_out)) != hipSuccess)
+    if ((e = launch_reduce(a.chunks, (int)b.chunks.size(), a.partial, p.k, ctr + 1, res, st, b.n_groups, b.n_surr, pv,
+                           ctr + 2, err_out)) != hipSuccess)
         return hip_fail(e, "reduce launch");
     if (out_dst != nullptr)
         e = hipMemcpyAsync(out_dst, res, sizeof(double) * (b.n_results + b.n_groups), hipMemcpyDefault, st);

@@ -93,12 +93,19 @@ struct SearchArgs {
     int32_t *cnt_out;           // optional per-point counts [3][cnt_stride]
     int64_t cnt_stride;
     const int32_t *perm_base;   // sorted-to-original point maps (per-point outputs only)
-    unsigned long long *work;   // optional: [0] += pairs evaluated in pass 1, [1] += in pass 2
+    unsigned long long *work;   // optional: [0] += pairs evaluated in pass 1, [1] += in pass 2 (a pair per chunk),
+                                // [2], [3] += the same counted once per set of chunks
     double *lte_out;            // optional per-point local TE (at out + original index)
     int32_t sorted;             // chunks are sorted by the first target-past coordinate
     int32_t n_parts;            // > 1: items split into n_parts queues (counter[p] heads queue p), see kQueues
     const int32_t *part_start;  // [n_parts + 1] first item of each queue (n_parts > 1)
+    const int32_t *set_first;   // non-null: chunk-set search; n_chunks counts sets, set c holds the chunks
+                                // [set_first[c], set_first[c+1]) (at most kSetVariants), item_start is per set
 };
+
+// Chunks of one window searched together by the chunk-set search (they share the
+// (y_t', Y_past) block and its order and differ in the source block).
+constexpr int kSetVariants = 4;
 
 // Work queues of a batched search: one per XCD of an MI355X.  Workgroups are
 // dispatched to the XCDs round-robin, so the waves of workgroup g start on queue
@@ -145,7 +152,10 @@ hipError_t launch_pvalues(const double *results, int n_groups, int n_surr, doubl
 hipError_t launch_argmax_u(const double *results, int n_groups, int n_u, const int32_t *u_values, int32_t *u_sel,
                            hipStream_t st);
 bool search_supported(int d_y, int d_x, int k, int slots);
-unsigned long long *work_counters();   // this device's evaluated-pair counters (measurement)
+bool search_sets_supported(int d_y, int d_x, int k);
+// Resident workgroups per compute unit of the chunk-set search (0 if unknown).
+int search_sets_occupancy(int d_y, int d_x, int slots, int waves_per_wg);
+unsigned long long *work_counters();   // this device's evaluated-pair counters [4] (measurement)
 
 // Search launch bracketed by profiling events when measurement is enabled (te_profile.cpp).
 hipError_t launch_search_timed(const SearchArgs &a, int d_y, int d_x, const SearchConfig &cfg, int grid_waves,

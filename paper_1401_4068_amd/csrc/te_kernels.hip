@@ -653,6 +653,390 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
     if (a.work != nullptr && lane == 0) {
         atomicAdd(a.work, work1);
         atomicAdd(a.work + 1, work2);
+        atomicAdd(a.work + 2, work1);
+        atomicAdd(a.work + 3, work2);
+    }
+}
+
+// ------------------------------------------------ the search over chunk sets
+//
+// The chunks of one window (its original and its surrogates, or its delays)
+// share the (y_t', Y_past) block and its sorted order and differ only in the
+// source block.  This variant searches a set of up to V such chunks per work
+// item: for every (reference, candidate) pair the target-future and
+// target-past differences are taken once, and only the source-past part is
+// evaluated per chunk.  Radii, counts and per-item sums are those of the
+// single-chunk search bit for bit (the same float operations decide every
+// comparison; only the order in which independent pairs are visited and which
+// lanes share a step differ).  Sorted chunks only.
+//
+//   d_J(v) = max(d_TP, d_S(v)),  d_TP = max(d_T, d_P)
+//   n_TP  counts [d_TP < eps_v],  n_PS counts [max(d_P, d_S(v)) < eps_v]
+//
+// A set is a run of consecutive chunk descriptors [set_first[c], set_first[c+1]);
+// its first descriptor supplies tp, ld, n, item0 and block0, each descriptor
+// its own s and pbase.  Sets with fewer than V chunks repeat their last chunk
+// in the unused variant slots and do not store those slots' sums.
+
+template <int DY, int DX, int V, int SLOTS>
+__global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_sets_kernel(SearchArgs a)
+{
+    constexpr int DT = 1 + DY;                 // shared coordinates: y_t' and the target past
+    constexpr int KP1 = 5;                     // k = 4: the k+1 smallest distances, self included
+    constexpr int NR = DT + V * DX + V;        // LDS row: shared coordinates, V source blocks, V radii
+    constexpr int RW = (NR + 3) & ~3;
+    constexpr int MO = DT > DX ? DT : DX;      // coordinate offsets shared by the target and source blocks
+    extern __shared__ __attribute__((aligned(16))) float rows[];   // waves per workgroup x 64 x RW floats
+    const int lane = threadIdx.x & (kWave - 1);
+
+    const int nq = a.n_parts > 1 ? a.n_parts : 1;
+    int qp = (int)(blockIdx.x % (unsigned)nq);
+    int drained = 0;
+    int last_ci = 0, last_lo = 0, last_hi = 0;
+    unsigned long long work1 = 0, work2 = 0, shared1 = 0, shared2 = 0;
+    for (;;) {
+        int q = 0;
+        if (lane == 0)
+            q = atomicAdd(a.counter + qp, 1);
+        q = __builtin_amdgcn_readlane(q, 0);
+        if (nq > 1) {
+            q += uload_i(a.part_start + qp);
+            if (q >= uload_i(a.part_start + qp + 1)) {
+                if (++drained >= nq)
+                    break;
+                qp = qp + 1 == nq ? 0 : qp + 1;
+                continue;
+            }
+        } else if (q >= a.n_items) {
+            break;
+        }
+        if (q < last_lo || q >= last_hi) {
+            last_ci = find_chunk(a.item_start, a.n_chunks, q);
+            last_lo = uload_i(a.item_start + last_ci);
+            last_hi = last_ci + 1 < a.n_chunks ? uload_i(a.item_start + last_ci + 1) : a.n_items;
+        }
+        const int c0 = uload_i(a.set_first + last_ci);
+        const int cnt = uload_i(a.set_first + last_ci + 1) - c0;   // chunks in the set, 1..V
+        const char *w0 = reinterpret_cast<const char *>(a.chunks + c0);
+        const int64_t tp = uload_l(reinterpret_cast<const int64_t *>(w0 + offsetof(ChunkDesc, tp)));
+        const int64_t ld = uload_l(reinterpret_cast<const int64_t *>(w0 + offsetof(ChunkDesc, ld)));
+        const int n = uload_i(reinterpret_cast<const int32_t *>(w0 + offsetof(ChunkDesc, n)));
+        const int item0 = uload_i(reinterpret_cast<const int32_t *>(w0 + offsetof(ChunkDesc, item0)));
+        const int block0 = uload_i(reinterpret_cast<const int32_t *>(w0 + offsetof(ChunkDesc, block0)));
+        const float *tb = a.base + tp;                 // target block of the set
+        const float *sb[V];                            // source block of each variant
+        int64_t pb[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const char *wv = reinterpret_cast<const char *>(a.chunks + c0 + min(v, cnt - 1));
+            sb[v] = a.base + uload_l(reinterpret_cast<const int64_t *>(wv + offsetof(ChunkDesc, s)));
+            pb[v] = uload_l(reinterpret_cast<const int64_t *>(wv + offsetof(ChunkDesc, pbase)));
+        }
+        uint32_t moff[MO];                             // byte offset of coordinate m within a block
+#pragma unroll
+        for (int m = 0; m < MO; ++m)
+            moff[m] = (uint32_t)((int64_t)m * ld * 4);
+
+        int blk = q - item0 + block0;
+        const int nb = (n + kWave - 1) / kWave;
+        if (block0 == 0 && last_hi - last_lo == nb) {
+            // middle blocks (densest in the p0 order) first, as in the single-chunk search
+            const int mid = nb >> 1, kk = blk;
+            const int pairs = min(mid, nb - mid);
+            if (kk < 2 * pairs)
+                blk = (kk & 1) ? mid - 1 - (kk >> 1) : mid + (kk >> 1);
+            else
+                blk = nb - mid > mid ? mid + pairs + (kk - 2 * pairs) : mid - 1 - pairs - (kk - 2 * pairs);
+        }
+        const int r0 = blk * kWave;
+
+        // ---- pass 1: lane = reference i
+        const int i = r0 + lane;
+        const bool valid = i < n;
+        const int ii = valid ? i : n - 1;
+        float rt[DT];
+        float rs[V][DX];
+#pragma unroll
+        for (int m = 0; m < DT; ++m)
+            rt[m] = tb[(int64_t)m * ld + ii];
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+            for (int m = 0; m < DX; ++m)
+                rs[v][m] = sb[v][(int64_t)m * ld + ii];
+        float best[V][KP1];
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+            for (int s = 0; s < KP1; ++s)
+                best[v][s] = kInf;
+        // largest current k+1-th distance over the variants: a candidate farther
+        // than it in p0 is of no use to any variant
+        auto curmax = [&]() {
+            float c = best[0][KP1 - 1];
+#pragma unroll
+            for (int v = 1; v < V; ++v)
+                c = fmaxf(c, best[v][KP1 - 1]);
+            return c;
+        };
+        // four consecutive candidates j..j+3: target coordinates ct, source coordinates cs
+        auto load4 = [&](int j, float (&ct)[4][DT], float (&cs)[V][4][DX]) {
+            const uint32_t off = (uint32_t)j * 4u;
+#pragma unroll
+            for (int m = 0; m < DT; ++m) {
+                const f4v x = uload4_at(tb, moff[m] + off);
+                ct[0][m] = x.x;
+                ct[1][m] = x.y;
+                ct[2][m] = x.z;
+                ct[3][m] = x.w;
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+#pragma unroll
+                for (int m = 0; m < DX; ++m) {
+                    const f4v x = uload4_at(sb[v], moff[m] + off);
+                    cs[v][0][m] = x.x;
+                    cs[v][1][m] = x.y;
+                    cs[v][2][m] = x.z;
+                    cs[v][3][m] = x.w;
+                }
+        };
+        auto visit4 = [&](const float (&ct)[4][DT], const float (&cs)[V][4][DX]) {
+            float dtp[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                float d = absdiff(rt[0], ct[u][0]);
+#pragma unroll
+                for (int m = 1; m < DT; ++m)
+                    d = fmaxf(d, absdiff(rt[m], ct[u][m]));
+                dtp[u] = d;
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                float dj[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    float d = absdiff(rs[v][0], cs[v][u][0]);
+#pragma unroll
+                    for (int m = 1; m < DX; ++m)
+                        d = fmaxf(d, absdiff(rs[v][m], cs[v][u][m]));
+                    dj[u] = fmaxf(dtp[u], d);
+                }
+                const float mn = fminf(fminf(dj[0], dj[1]), fminf(dj[2], dj[3]));
+                if (ballot(mn < best[v][KP1 - 1])) {
+                    keep_branch();
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (ballot(dj[u] < best[v][KP1 - 1])) {
+                            keep_branch();
+                            insert_sorted<KP1>(best[v], dj[u]);
+                        }
+                }
+            }
+        };
+        auto visit1 = [&](int j) {
+            float dtp = absdiff(rt[0], uload(tb + j));
+#pragma unroll
+            for (int m = 1; m < DT; ++m)
+                dtp = fmaxf(dtp, absdiff(rt[m], uload(tb + (int64_t)m * ld + j)));
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                float d = absdiff(rs[v][0], uload(sb[v] + j));
+#pragma unroll
+                for (int m = 1; m < DX; ++m)
+                    d = fmaxf(d, absdiff(rs[v][m], uload(sb[v] + (int64_t)m * ld + j)));
+                const float dj = fmaxf(dtp, d);
+                if (ballot(dj < best[v][KP1 - 1])) {
+                    keep_branch();
+                    insert_sorted<KP1>(best[v], dj);
+                }
+            }
+        };
+
+        // the block's own points, then outward in p0 order, forward then backward;
+        // a direction stops at the first group whose farthest candidate no lane of
+        // any variant could use (p0 is coordinate 1, a target-past coordinate)
+        const int e0 = min(n, r0 + kWave);
+        int j = r0;
+        for (; j + 4 <= e0; j += 4) {
+            float ct[4][DT], cs[V][4][DX];
+            load4(j, ct, cs);
+            visit4(ct, cs);
+        }
+        for (; j < e0; ++j)
+            visit1(j);
+        int f = e0;
+        bool go = f < n;
+        while (go && f + 4 <= n) {
+            float ct[4][DT], cs[V][4][DX];
+            load4(f, ct, cs);
+            visit4(ct, cs);
+            f += 4;
+            go = f < n && ballot(absdiff(rt[1], ct[3][1]) < curmax()) != 0;
+        }
+        while (go && f < n) {
+            const float p0 = uload(tb + ld + f);
+            visit1(f);
+            ++f;
+            go = f < n && ballot(absdiff(rt[1], p0) < curmax()) != 0;
+        }
+        int b = r0;
+        go = b > 0;
+        while (go && b >= 4) {
+            float ct[4][DT], cs[V][4][DX];
+            load4(b - 4, ct, cs);
+            visit4(ct, cs);
+            b -= 4;
+            go = b > 0 && ballot(absdiff(rt[1], ct[0][1]) < curmax()) != 0;
+        }
+        while (go && b > 0) {
+            const float p0 = uload(tb + ld + b - 1);
+            visit1(b - 1);
+            --b;
+            go = b > 0 && ballot(absdiff(rt[1], p0) < curmax()) != 0;
+        }
+        const int visited = f - b;
+        float eps[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            eps[v] = best[v][KP1 - 1];
+        const float emax = curmax();
+
+        // ---- pass 2: lane = candidate, references uniform from this wave's LDS rows
+        float *myrows = rows + (threadIdx.x / kWave) * (kWave * RW);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int m = 0; m < DT; ++m)
+            myrows[lane * RW + m] = rt[m];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+#pragma unroll
+            for (int m = 0; m < DX; ++m)
+                myrows[lane * RW + DT + v * DX + m] = rs[v][m];
+            myrows[lane * RW + DT + V * DX + v] = eps[v];
+        }
+        __builtin_amdgcn_wave_barrier();
+
+        // candidate range: outside it every point is at |fl32(p0_i - p0_j)| >= the
+        // largest radius of every reference of the block
+        int hi = f;
+        while (hi - kWave >= e0 && !ballot(valid && absdiff(rt[1], uload(tb + ld + hi - kWave)) < emax))
+            hi -= kWave;
+        int lo = b;
+        while (lo + kWave <= r0 && !ballot(valid && absdiff(rt[1], uload(tb + ld + lo + kWave - 1)) < emax))
+            lo += kWave;
+
+        const int nref = min(kWave, n - r0);
+        uint32_t accP[V], accTP[V], accPS[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            accP[v] = accTP[v] = accPS[v] = 0;
+        unsigned long long evaluated2 = 0;
+        for (int t0 = lo; t0 < hi; t0 += kWave * SLOTS) {
+            float ct[SLOTS][DT], cs[SLOTS][V][DX];
+#pragma unroll
+            for (int sl = 0; sl < SLOTS; ++sl) {
+                const int idx = t0 + sl * kWave + lane;
+                const bool ok = idx < hi;
+                const int ic = ok ? idx : n - 1;
+#pragma unroll
+                for (int m = 0; m < DT; ++m) {
+                    const float x = tb[(int64_t)m * ld + ic];
+                    ct[sl][m] = ok ? x : kInf;
+                }
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+#pragma unroll
+                    for (int m = 0; m < DX; ++m) {
+                        const float x = sb[v][(int64_t)m * ld + ic];
+                        cs[sl][v][m] = ok ? x : kInf;
+                    }
+            }
+            const float tlo = uload(tb + ld + t0);
+            const float thi = uload(tb + ld + min(t0 + kWave * SLOTS, hi) - 1);
+            const bool reach = valid && !(tlo - rt[1] >= emax || rt[1] - thi >= emax);
+            uint64_t todo = ballot(reach);
+            evaluated2 += (unsigned long long)__builtin_popcountll(todo) *
+                          (unsigned long long)min(kWave * SLOTS, hi - t0);
+            uint32_t tP[V], tTP[V], tPS[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                tP[v] = tTP[v] = tPS[v] = 0;
+            while (todo != 0) {
+                const int r = __builtin_ctzll(todo);
+                todo &= todo - 1;
+                float rr[RW];
+                {
+                    const f4v *rowv = reinterpret_cast<const f4v *>(myrows + r * RW);
+#pragma unroll
+                    for (int x = 0; x < RW / 4; ++x) {
+                        const f4v q4 = rowv[x];
+                        rr[4 * x + 0] = q4.x;
+                        rr[4 * x + 1] = q4.y;
+                        rr[4 * x + 2] = q4.z;
+                        rr[4 * x + 3] = q4.w;
+                    }
+                }
+                uint32_t sP[V], sTP[V], sPS[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    sP[v] = sTP[v] = sPS[v] = 0;
+#pragma unroll
+                for (int sl = 0; sl < SLOTS; ++sl) {
+                    float dp = absdiff(rr[1], ct[sl][1]);
+#pragma unroll
+                    for (int m = 2; m < DT; ++m)
+                        dp = fmaxf(dp, absdiff(rr[m], ct[sl][m]));
+                    const float dtp = fmaxf(absdiff(rr[0], ct[sl][0]), dp);
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        float ds = absdiff(rr[DT + v * DX], cs[sl][v][0]);
+#pragma unroll
+                        for (int m = 1; m < DX; ++m)
+                            ds = fmaxf(ds, absdiff(rr[DT + v * DX + m], cs[sl][v][m]));
+                        const float er = rr[DT + V * DX + v];
+                        sP[v] += (uint32_t)__builtin_popcountll(ballot(dp < er));
+                        sTP[v] += (uint32_t)__builtin_popcountll(ballot(dtp < er));
+                        sPS[v] += (uint32_t)__builtin_popcountll(ballot(fmaxf(dp, ds) < er));
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    tP[v] = writelane(tP[v], sP[v], r);
+                    tTP[v] = writelane(tTP[v], sTP[v], r);
+                    tPS[v] = writelane(tPS[v], sPS[v], r);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                accP[v] += tP[v];
+                accTP[v] += tTP[v];
+                accPS[v] += tPS[v];
+            }
+        }
+
+        // ---- digamma terms per variant, summed over the item in fixed order
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const uint32_t self = eps[v] > 0.0f ? 1u : 0u;
+            double term = 0.0;
+            if (valid)
+                term = psi_of_count((int)(accP[v] - self)) - psi_of_count((int)(accTP[v] - self)) -
+                       psi_of_count((int)(accPS[v] - self));
+            const double sum = wave_sum(term);
+            if (lane == 0 && v < cnt)
+                a.partial[pb[v] + blk] = sum;
+        }
+        work1 += (unsigned long long)visited * (unsigned long long)nref * (unsigned long long)cnt;
+        work2 += evaluated2 * (unsigned long long)cnt;
+        shared1 += (unsigned long long)visited * (unsigned long long)nref;
+        shared2 += evaluated2;
+    }
+    if (a.work != nullptr && lane == 0) {
+        atomicAdd(a.work, work1);
+        atomicAdd(a.work + 1, work2);
+        atomicAdd(a.work + 2, shared1);
+        atomicAdd(a.work + 3, shared2);
     }
 }
 
@@ -1318,10 +1702,40 @@ search_fn pick_any(int d_y, int d_x, int k, int slots, bool sorted)
     return nullptr;
 }
 
+// Chunk-set search: V = kSetVariants chunks per item, k = 4, sorted chunks; two or
+// four candidate slots per lane in the counting pass (the tuned slot count 4 -> 2,
+// 8 or 16 -> 4).
+template <int SLOTS>
+search_fn pick_sets_slots(int d_y, int d_x)
+{
+#define TE_CASE(A, B) \
+    if (d_y == A && d_x == B) return search_sets_kernel<A, B, kSetVariants, SLOTS>;
+    TE_CASE(1, 1) TE_CASE(1, 2) TE_CASE(1, 3) TE_CASE(1, 4)
+    TE_CASE(2, 1) TE_CASE(2, 2) TE_CASE(2, 3) TE_CASE(2, 4)
+    TE_CASE(3, 1) TE_CASE(3, 2) TE_CASE(3, 3) TE_CASE(3, 4)
+    TE_CASE(4, 1) TE_CASE(4, 2) TE_CASE(4, 3) TE_CASE(4, 4)
+#undef TE_CASE
+    return nullptr;
+}
+
+search_fn pick_sets(int d_y, int d_x, int slots)
+{
+    return slots <= 4 ? pick_sets_slots<2>(d_y, d_x) : pick_sets_slots<4>(d_y, d_x);
+}
+
+// LDS bytes of the chunk-set search per workgroup (its rows are dynamic shared memory).
+size_t sets_lds_bytes(int d_y, int d_x, int waves_per_wg)
+{
+    const int nr = 1 + d_y + kSetVariants * d_x + kSetVariants;
+    return (size_t)waves_per_wg * kWave * (size_t)((nr + 3) & ~3) * sizeof(float);
+}
+
 }  // namespace
 
-// Device counters of evaluated pairs for the measurement hook (one copy per device).
-__device__ unsigned long long g_work_counters[2];
+// Device counters of evaluated pairs for the measurement hook (one copy per device):
+// [0] pass-1 and [1] pass-2 (reference, candidate, chunk) triples, [2] and [3] the
+// (reference, candidate) pairs whose shared coordinates were evaluated once for them.
+__device__ unsigned long long g_work_counters[4];
 
 unsigned long long *work_counters()
 {
@@ -1345,14 +1759,35 @@ int search_occupancy(int d_y, int d_x, int k, int slots, int waves_per_wg)
     return blocks;
 }
 
+bool search_sets_supported(int d_y, int d_x, int k) { return k == 4 && pick_sets(d_y, d_x, 4) != nullptr; }
+
+int search_sets_occupancy(int d_y, int d_x, int slots, int waves_per_wg)
+{
+    search_fn f = pick_sets(d_y, d_x, slots);
+    if (!f)
+        return 0;
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, f, kWave * waves_per_wg,
+                                                     sets_lds_bytes(d_y, d_x, waves_per_wg)) != hipSuccess)
+        return 0;
+    return blocks;
+}
+
 hipError_t launch_search(const SearchArgs &a, int d_y, int d_x, const SearchConfig &cfg, int grid_waves,
                          hipStream_t st)
 {
+    const int wpg = cfg.waves_per_wg;
+    const int blocks = (grid_waves + wpg - 1) / wpg;
+    if (a.set_first != nullptr) {
+        search_fn f = (a.k == 4 && a.sorted) ? pick_sets(d_y, d_x, cfg.slots) : nullptr;
+        if (!f)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(f, dim3(blocks), dim3(kWave * wpg), sets_lds_bytes(d_y, d_x, wpg), st, a);
+        return hipGetLastError();
+    }
     search_fn f = pick_any(d_y, d_x, a.k, cfg.slots, a.sorted != 0);
     if (!f)
         return hipErrorInvalidValue;
-    const int wpg = cfg.waves_per_wg;
-    const int blocks = (grid_waves + wpg - 1) / wpg;
     hipLaunchKernelGGL(f, dim3(blocks), dim3(kWave * wpg), 0, st, a);
     return hipGetLastError();
 }

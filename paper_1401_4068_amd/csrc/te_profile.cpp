@@ -89,10 +89,10 @@ te_status te_profile_enable(int32_t on)
     return TE_OK;
 }
 
-te_status te_profile_work(int64_t *pass1_pairs, int64_t *pass2_pairs, int32_t reset)
+te_status te_profile_work_all(int64_t *counts, int32_t reset)
 {
     std::lock_guard<std::mutex> lk(g_mu);
-    unsigned long long w[2] = {0, 0};
+    unsigned long long w[4] = {0, 0, 0, 0};
     if (g_work) {
         if (hipDeviceSynchronize() != hipSuccess ||
             hipMemcpy(w, g_work, sizeof w, hipMemcpyDeviceToHost) != hipSuccess)
@@ -100,10 +100,22 @@ te_status te_profile_work(int64_t *pass1_pairs, int64_t *pass2_pairs, int32_t re
         if (reset && hipMemset(g_work, 0, sizeof w) != hipSuccess)
             return TE_ERR_DEVICE;
     }
+    if (counts)
+        for (int i = 0; i < 4; ++i)
+            counts[i] = (int64_t)w[i];
+    return TE_OK;
+}
+
+te_status te_profile_work(int64_t *pass1_pairs, int64_t *pass2_pairs, int32_t reset)
+{
+    int64_t w[4];
+    const te_status s = te_profile_work_all(w, reset);
+    if (s != TE_OK)
+        return s;
     if (pass1_pairs)
-        *pass1_pairs = (int64_t)w[0];
+        *pass1_pairs = w[0];
     if (pass2_pairs)
-        *pass2_pairs = (int64_t)w[1];
+        *pass2_pairs = w[1];
     return TE_OK;
 }
 

@@ -45,11 +45,14 @@ struct Batch {
     int64_t n_sigma = 0;                  // int32 entries of the sorted-to-original maps
     int64_t n_scratch = 0;                // uint64 sort scratch entries
     int64_t n_items = 0;
+    bool use_sets = false;                // chunk-set search: a window's chunks kSetVariants at a time
+    std::vector<int32_t> set_first;       // [n_sets + 1] chunk range of each set (use_sets)
+    int64_t n_partials = 0;               // per-item partial sums: one per 64-point block of every chunk
     std::vector<int32_t> part_start;      // [kQueues + 1] item ranges of the XCD work queues
     // byte offsets inside the workspace
     size_t off_coords = 0, off_tables = 0, off_chunks = 0, off_items = 0, off_tasks = 0, off_ptasks = 0,
            off_perm = 0, off_sorts = 0, off_partial = 0, off_results = 0, off_pv = 0, off_ctr = 0, off_sigma = 0,
-           off_scratch = 0, off_parts = 0, off_qctr = 0, off_errout = 0;
+           off_scratch = 0, off_parts = 0, off_qctr = 0, off_errout = 0, off_sets = 0;
     size_t tables_bytes = 0;
     size_t total_bytes = 0;
     std::vector<char> host_tables;
@@ -88,6 +91,7 @@ struct BatchOptions {
     bool local_outputs = false;                   // per-point local TE of the originals
     const std::vector<int32_t> *delays = nullptr; // variants: the original at each of these source delays
     bool delay_from_device = false;               // source delay of group gi read from u_dev[gi]
+    bool allow_sets = true;                       // chunk-set search where the plan allows it
 };
 
 // Byte offsets of the plain per-chunk path's workspace (Plan::plain_layout).
@@ -124,6 +128,11 @@ struct Plan {
     te_status build_group_batch(const std::vector<int> &groups, int n_surr, Batch *b,
                                 const BatchOptions &opt = BatchOptions()) const;
     int grid_waves(int64_t n_items) const;
+    // the window's chunks can be searched as sets (sorted, k = 4, no x_t in the target block)
+    bool sets_eligible() const;
+    // launch shape of a batch: the plan's, with the resident workgroups capped at the
+    // chunk-set search's occupancy for batches that use it
+    SearchConfig batch_config(const Batch &b) const;
     // tables_src: upload the tables from this pinned copy instead of through `stage`;
     // out_dst: copy the results block (estimates [group][original, surrogates], then
     // p-values) there (device or pinned host) instead of into `stage`.

@@ -310,7 +310,7 @@ te_status te_plan_autotune(te_plan plan, const float *x, const float *y, const i
             break;
         groups.swap(trial);
         b = std::move(t);
-        if (b.n_items >= want_items)
+        if (b.n_partials >= want_items)
             break;
     }
     if (groups.empty())
@@ -329,7 +329,10 @@ te_status te_plan_autotune(te_plan plan, const float *x, const float *y, const i
     const int wpg_set[] = {1, 2, 4};
     for (int sl : slot_set)
         for (int wpg : wpg_set) {
-            const int occ = search_occupancy(P.dy_eff(), P.p.d_x, P.p.k, sl, wpg);
+            if (b.use_sets && sl == 16)                  // the chunk-set search runs 16 slots as 8
+                continue;
+            const int occ = b.use_sets ? search_sets_occupancy(P.dy_eff(), P.p.d_x, sl, wpg)
+                                       : search_occupancy(P.dy_eff(), P.p.d_x, P.p.k, sl, wpg);
             if (occ < 1)
                 continue;
             // every occupancy from full down to half, in whole waves per SIMD: a

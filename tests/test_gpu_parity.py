@@ -598,3 +598,68 @@ def test_plain_per_chunk_path_equals_batched(te, cond):
         for u, v in zip(ref, got):
             np.testing.assert_array_equal(u, v)
     np.testing.assert_array_equal(plan.estimate(x, y), ref[0])
+
+
+# ------------------------------------------------------------ chunk sets
+
+def _both_ways(te, monkeypatch, wl, run):
+    """run(plan) with the window's chunks searched in sets (the default) and one chunk
+    at a time (TE_NO_SETS=1): the results must be identical bit for bit."""
+    monkeypatch.setenv("TE_NO_SETS", "1")
+    single = run(te.Plan.from_workload(wl))
+    monkeypatch.delenv("TE_NO_SETS")
+    sets = run(te.Plan.from_workload(wl))
+    for u, v in zip(single, sets):
+        if u is None:
+            assert v is None
+        else:
+            np.testing.assert_array_equal(u, v)
+    return sets
+
+
+@pytest.mark.parametrize("d_y,d_x,S", [(1, 1, 2), (2, 4, 3), (4, 4, 4), (4, 1, 7), (3, 3, 5), (2, 2, 1)])
+def test_chunk_sets_equal_single_chunk_search(te, monkeypatch, d_y, d_x, S):
+    """Sets of up to four chunks of a window (original + surrogates, full and partial sets)
+    against the single-chunk search, on uneven windows with ragged 64-point blocks; the set
+    path is also checked against the oracle."""
+    wl = synth.generic((6061, d_y, d_x, S), R=60, T=70, d_y=d_y, d_x=d_x, starts=(30, 41, 55),
+                       windows=(13, 7, 10), trials=(60, 47, 33), n_surrogates=S)
+    say("sets case", dict(d_y=d_y, d_x=d_x, S=S, sizes=wl.chunk_sizes().tolist()))
+    x, y, perms = dev(wl)
+    got = _both_ways(te, monkeypatch, wl, lambda plan: plan.surrogates(x, y, perms))
+    _compare(wl, *got)
+
+
+def test_chunk_sets_async_split_and_counters(te, monkeypatch):
+    import torch
+    wl = synth.uneven_surrogates(R=150, T=60, n_points=3, n_surrogates=6, n_lo=300, n_hi=3000)
+    x, y, perms = dev(wl)
+    G, S = wl.n_pairs * wl.n_points, wl.n_surrogates
+
+    def run(plan):
+        full, minimum, _ = plan.workspace_bytes()
+        out = torch.empty(G * (S + 1) + G, dtype=torch.float64, device="cuda")
+        plan.surrogates_async(x, y, perms, out=out)
+        torch.cuda.synchronize()
+        ws = torch.empty(minimum, dtype=torch.uint8, device="cuda")
+        split = plan.surrogates(x, y, perms, ws=ws)
+        return [out.cpu().numpy()] + list(split)
+    _both_ways(te, monkeypatch, wl, run)
+    # work counters: a set evaluates its target comparisons once for all its chunks
+    plan = te.Plan.from_workload(wl)
+    te.profile_enable(False, work=True)
+    te.profile_work_all(reset=True)
+    plan.surrogates(x, y, perms)
+    w = te.profile_work_all(reset=True)
+    te.profile_enable(False)
+    say("counters", w)
+    assert 0 < w[2] < w[0] and 0 < w[3] < w[1]
+    assert w[0] <= 4 * w[2] and w[1] <= 4 * w[3]
+
+
+def test_chunk_sets_in_delay_scan(te, monkeypatch):
+    wl = _scan_workload()
+    u_values = [1, 2, 3, 4, 5, 6, 7, 8, 3]
+    x, y, perms = dev(wl)
+    got = _both_ways(te, monkeypatch, wl, lambda plan: plan.delay_scan(x, y, u_values, perms))
+    _check_scan(wl, u_values, got)

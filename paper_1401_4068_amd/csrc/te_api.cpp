@@ -142,7 +142,7 @@ void Batch::finish_layout()
         const int64_t nb = (d.n + kWave - 1) / kWave;
         // a new work unit: every chunk without sets; with sets, when the previous set is
         // full or belongs to another window (the stable LPT order keeps a window's chunks together)
-        const bool start = !use_sets || set_first.empty() || (int)sorted.size() - set_first.back() >= kSetVariants ||
+        const bool start = !use_sets || set_first.empty() || (int)sorted.size() - set_first.back() >= set_v ||
                            sorted.back().tp != d.tp || sorted.back().n != d.n;
         if (start) {
             d.item0 = (int32_t)n_items;
@@ -255,6 +255,7 @@ te_status Plan::build_group_batch(const std::vector<int> &groups, int n_surr, Ba
     b->n_groups = (int)groups.size();
     b->n_surr = n_surr;
     b->use_sets = opt.allow_sets && !opt.local_outputs && n_surr >= 1 && sets_eligible();
+    b->set_v = set_variants(dy_eff(), p.d_x);
     b->n_results = b->n_groups * (n_surr + 1);
     b->groups = groups;
     int64_t fl = 0;

@@ -100,12 +100,18 @@ struct SearchArgs {
     int32_t n_parts;            // > 1: items split into n_parts queues (counter[p] heads queue p), see kQueues
     const int32_t *part_start;  // [n_parts + 1] first item of each queue (n_parts > 1)
     const int32_t *set_first;   // non-null: chunk-set search; n_chunks counts sets, set c holds the chunks
-                                // [set_first[c], set_first[c+1]) (at most kSetVariants), item_start is per set
+                                // [set_first[c], set_first[c+1]) (at most set_variants(d_y, d_x)), item_start is per set
 };
 
 // Chunks of one window searched together by the chunk-set search (they share the
-// (y_t', Y_past) block and its order and differ in the source block).
-constexpr int kSetVariants = 4;
+// (y_t', Y_past) block and its order and differ in the source block): as many as
+// keep a group of four candidates' coordinates, 4 (1 + d_y + V d_x) values, within
+// 64 scalar registers, two to four.
+constexpr int set_variants(int d_y, int d_x)
+{
+    return (15 - d_y) / d_x >= 4 ? 4 : ((15 - d_y) / d_x <= 2 ? 2 : (15 - d_y) / d_x);
+}
+constexpr int kMaxSetVariants = 4;
 
 // Work queues of a batched search: one per XCD of an MI355X.  Workgroups are
 // dispatched to the XCDs round-robin, so the waves of workgroup g start on queue

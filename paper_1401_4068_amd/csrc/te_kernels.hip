@@ -1702,14 +1702,14 @@ search_fn pick_any(int d_y, int d_x, int k, int slots, bool sorted)
     return nullptr;
 }
 
-// Chunk-set search: V = kSetVariants chunks per item, k = 4, sorted chunks; two or
+// Chunk-set search: V = set_variants(d_y, d_x) chunks per item, k = 4, sorted chunks; two or
 // four candidate slots per lane in the counting pass (the tuned slot count 4 -> 2,
 // 8 or 16 -> 4).
 template <int SLOTS>
 search_fn pick_sets_slots(int d_y, int d_x)
 {
 #define TE_CASE(A, B) \
-    if (d_y == A && d_x == B) return search_sets_kernel<A, B, kSetVariants, SLOTS>;
+    if (d_y == A && d_x == B) return search_sets_kernel<A, B, set_variants(A, B), SLOTS>;
     TE_CASE(1, 1) TE_CASE(1, 2) TE_CASE(1, 3) TE_CASE(1, 4)
     TE_CASE(2, 1) TE_CASE(2, 2) TE_CASE(2, 3) TE_CASE(2, 4)
     TE_CASE(3, 1) TE_CASE(3, 2) TE_CASE(3, 3) TE_CASE(3, 4)
@@ -1726,7 +1726,8 @@ search_fn pick_sets(int d_y, int d_x, int slots)
 // LDS bytes of the chunk-set search per workgroup (its rows are dynamic shared memory).
 size_t sets_lds_bytes(int d_y, int d_x, int waves_per_wg)
 {
-    const int nr = 1 + d_y + kSetVariants * d_x + kSetVariants;
+    const int v = set_variants(d_y, d_x);
+    const int nr = 1 + d_y + v * d_x + v;
     return (size_t)waves_per_wg * kWave * (size_t)((nr + 3) & ~3) * sizeof(float);
 }
 

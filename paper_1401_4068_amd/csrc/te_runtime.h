@@ -45,7 +45,8 @@ struct Batch {
     int64_t n_sigma = 0;                  // int32 entries of the sorted-to-original maps
     int64_t n_scratch = 0;                // uint64 sort scratch entries
     int64_t n_items = 0;
-    bool use_sets = false;                // chunk-set search: a window's chunks kSetVariants at a time
+    bool use_sets = false;                // chunk-set search: a window's chunks set_v at a time
+    int set_v = 1;                        // chunks per set (set_variants of the plan's dimensions)
     std::vector<int32_t> set_first;       // [n_sets + 1] chunk range of each set (use_sets)
     int64_t n_partials = 0;               // per-item partial sums: one per 64-point block of every chunk
     std::vector<int32_t> part_start;      // [kQueues + 1] item ranges of the XCD work queues

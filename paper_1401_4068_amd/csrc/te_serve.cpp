@@ -74,6 +74,24 @@ struct Arena {
         }
         return false;
     }
+    // the same from the top of the highest free block that fits: long-lived blocks (kernel
+    // class step tables) stay apart from job regions, which are taken first-fit from below
+    bool alloc_high(size_t bytes, size_t *off)
+    {
+        bytes = align_up(std::max<size_t>(bytes, 1), 256);
+        for (auto it = free_.rbegin(); it != free_.rend(); ++it) {
+            if (it->second >= bytes) {
+                it->second -= bytes;
+                *off = it->first + it->second;
+                if (it->second == 0)
+                    free_.erase(std::next(it).base());
+                used += bytes;
+                peak = std::max(peak, used);
+                return true;
+            }
+        }
+        return false;
+    }
     void release(size_t off, size_t bytes)
     {
         bytes = align_up(std::max<size_t>(bytes, 1), 256);
@@ -106,8 +124,8 @@ struct Job {
     size_t off_x = 0, off_y = 0, off_perm = 0, off_batch = 0;
     int cls = 0;
     JobState state = QUEUED;
-    std::vector<int32_t> next_block;   // per chunk (schedule order): next block to schedule
-    size_t next_chunk = 0;             // first chunk with unscheduled blocks
+    std::vector<int32_t> next_block;   // per unit (chunk, or set of chunks; schedule order): next block
+    size_t next_chunk = 0;             // first unit with unscheduled blocks
     bool all_scheduled = false;
     hipEvent_t ready_ev = nullptr, done_ev = nullptr;
     void *stage = nullptr;
@@ -130,12 +148,15 @@ struct KernelClass {
     int d_y = 0, d_x = 0, k = 0;
     int cond = 0;                       // conditioning on x_t (d_y above includes it)
     bool sorted = true;
+    bool sets = false;                  // jobs searched as chunk sets (the chunk-set search kernel)
+    int set_v = 1;                      // chunks per set
     hipStream_t stream[2] = {nullptr, nullptr};   // steps alternate, so one step's tail overlaps the next
     hipEvent_t last_ev[2] = {nullptr, nullptr};   // completion of the last step issued on each stream
     SearchConfig cfg{};
     int in_flight = 0;
     int64_t max_items = 0;
     size_t table_cap = 0;
+    bool tables = false;                // table_off allocated in the arena (at the first admission of the class)
     size_t table_off[2] = {0, 0};
     void *stage[2] = {nullptr, nullptr};
     bool slot_busy[2] = {false, false};
@@ -185,7 +206,8 @@ struct Server {
     void wake_up();
     void sleep_until_woken(std::unique_lock<std::mutex> &lk, int ms);
     void drain_streams(const KernelClass *kc);
-    int class_of(const te_problem &p, bool sorted);
+    int class_of(const te_problem &p, bool sorted, bool sets, int set_v);
+    bool ensure_tables(KernelClass &c);
     bool admit_one(Job *j);
     void poll_setup();
     bool issue_step(int ci);
@@ -196,31 +218,32 @@ struct Server {
 };
 
 // Kernel class of a problem, created on first use (-1 if its step tables do not fit).
-int Server::class_of(const te_problem &p, bool sorted)
+int Server::class_of(const te_problem &p, bool sorted, bool sets, int set_v)
 {
     for (size_t i = 0; i < classes.size(); ++i)
         if (classes[i].d_y == p.d_y + p.cond_source && classes[i].d_x == p.d_x && classes[i].k == p.k &&
-            classes[i].sorted == sorted && classes[i].cond == p.cond_source)
+            classes[i].sorted == sorted && classes[i].cond == p.cond_source && classes[i].sets == sets)
             return (int)i;
     KernelClass c;
     c.sorted = sorted;
+    c.sets = sets;
+    c.set_v = sets ? set_v : 1;
     c.d_y = p.d_y + p.cond_source;                   // as the search sees it
     c.cond = p.cond_source;
     c.d_x = p.d_x;
     c.k = p.k;
-    if (!dry)
+    if (!dry) {
         c.cfg = default_config(dev, c.d_y, p.d_x, p.k, 16384);
-    c.max_items = (int64_t)std::max(1, dev.n_cu) * std::max(1, c.cfg.wg_per_cu) * std::max(1, c.cfg.waves_per_wg) * 16;
-    c.table_cap = align_up(sizeof(ChunkDesc) * (size_t)c.max_items, 16) +
-                  align_up(sizeof(int32_t) * (size_t)c.max_items, 16) + align_up(sizeof(int32_t) * (kQueues + 1), 16) +
-                  sizeof(int32_t) * kQueues + 64;
-    for (int sl = 0; sl < 2; ++sl) {
-        if (!alloc.alloc(c.table_cap, &c.table_off[sl])) {
-            for (int u = 0; u < sl; ++u)
-                alloc.release(c.table_off[u], c.table_cap);
-            return -1;
-        }
+        if (sets)
+            c.cfg.wg_per_cu = std::max(1, std::min(c.cfg.wg_per_cu,
+                                                   search_sets_occupancy(c.d_y, c.d_x, c.cfg.slots, c.cfg.waves_per_wg)));
     }
+    c.max_items = (int64_t)std::max(1, dev.n_cu) * std::max(1, c.cfg.wg_per_cu) * std::max(1, c.cfg.waves_per_wg) * 16;
+    // step table: chunk descriptors (at most max_items), piece starts, set ranges, queue bounds, queue heads
+    c.table_cap = align_up(sizeof(ChunkDesc) * (size_t)c.max_items, 16) +
+                  align_up(sizeof(int32_t) * (size_t)c.max_items, 16) +
+                  align_up(sizeof(int32_t) * ((size_t)c.max_items + 1), 16) + align_up(sizeof(int32_t) * (kQueues + 1), 16) +
+                  sizeof(int32_t) * kQueues + 64;
     if (!dry) {
         for (int sl = 0; sl < 2; ++sl) {
             hipStreamCreateWithFlags(&c.stream[sl], hipStreamNonBlocking);
@@ -230,6 +253,23 @@ int Server::class_of(const te_problem &p, bool sorted)
     }
     classes.push_back(c);
     return (int)classes.size() - 1;
+}
+
+// The class's two step tables in the arena, taken when its first job is admitted
+// (admission waits, like a job's footprint, while they do not fit).
+bool Server::ensure_tables(KernelClass &c)
+{
+    if (c.tables)
+        return true;
+    for (int sl = 0; sl < 2; ++sl) {
+        if (!alloc.alloc_high(c.table_cap, &c.table_off[sl])) {
+            for (int u = 0; u < sl; ++u)
+                alloc.release(c.table_off[u], c.table_cap);
+            return false;
+        }
+    }
+    c.tables = true;
+    return true;
 }
 
 static int embed_max_n(const Batch &b)
@@ -332,6 +372,8 @@ void Server::drain_streams(const KernelClass *kc)
 bool Server::admit_one(Job *j)
 {
     size_t off = 0;
+    if (!ensure_tables(classes[j->cls]))
+        return false;
     if (!alloc.alloc(j->footprint, &off))
         return false;
     j->region = off;
@@ -339,7 +381,7 @@ bool Server::admit_one(Job *j)
     resident.push_back(j);
     peak_slots = std::max<int64_t>(peak_slots, (int64_t)resident.size());
     Batch &b = j->batch;
-    j->next_block.assign(b.chunks.size(), 0);
+    j->next_block.assign(b.use_sets ? b.set_first.size() - 1 : b.chunks.size(), 0);
     j->next_chunk = 0;
     const bool inject = fault_staging > 0 && ++admissions == fault_staging;
     if (dry) {
@@ -432,8 +474,9 @@ void Server::poll_setup()
 bool Server::issue_step(int ci)
 {
     KernelClass &kc = classes[ci];
-    std::vector<ChunkDesc> tab;
-    std::vector<int32_t> starts;
+    std::vector<ChunkDesc> tab;          // chunk descriptors of the step's pieces
+    std::vector<ChunkDesc> leaders;      // first descriptor of each piece, n scaled by its chunks (queue costs)
+    std::vector<int32_t> starts, sfirst;
     std::vector<Job *> finishing, members;
     int64_t items = 0, pairs = 0;
     const int64_t max_items = kc.max_items;
@@ -449,35 +492,51 @@ bool Server::issue_step(int ci)
         Batch &b = j->batch;
         const int64_t fbase = dry ? 0 : (int64_t)((j->region + j->off_batch + b.off_coords) / sizeof(float));
         const int64_t pb = dry ? 0 : (int64_t)((j->region + j->off_batch + b.off_partial) / sizeof(double));
+        // units of work: single chunks, or the job's chunk sets in a set class
+        const size_t n_units = kc.sets ? b.set_first.size() - 1 : b.chunks.size();
         members.push_back(j);
-        while (j->next_chunk < b.chunks.size() && (pairs < step_pairs || items < min_items) && items < max_items) {
-            const size_t c = j->next_chunk;
-            const ChunkDesc &src = b.chunks[c];
+        while (j->next_chunk < n_units && (pairs < step_pairs || items < min_items) && items < max_items) {
+            const size_t u = j->next_chunk;
+            const int c0 = kc.sets ? b.set_first[u] : (int)u;
+            const int cnt = kc.sets ? b.set_first[u + 1] - c0 : 1;
+            const ChunkDesc &src = b.chunks[c0];
             const int nb = (src.n + kWave - 1) / kWave;
-            const int64_t per_block = (int64_t)kWave * src.n;
+            const int64_t per_block = (int64_t)kWave * src.n * cnt;
             int64_t want = std::max<int64_t>(1, (step_pairs - pairs) / std::max<int64_t>(per_block, 1));
             want = std::max<int64_t>(want, min_items - items);
             want = std::min<int64_t>(want, max_items - items);
-            const int take = (int)std::min<int64_t>(want, nb - j->next_block[c]);
-            ChunkDesc d = src;
-            d.tp += fbase;
-            d.s += fbase;
-            d.pbase += pb;
-            d.item0 = (int32_t)items;
-            d.block0 = j->next_block[c];
-            tab.push_back(d);
+            const int take = (int)std::min<int64_t>(want, nb - j->next_block[u]);
+            if ((int64_t)tab.size() + cnt > max_items)       // the descriptor table is full
+                break;
+            if (kc.sets)
+                sfirst.push_back((int32_t)tab.size());
+            for (int v = 0; v < cnt; ++v) {
+                ChunkDesc d = b.chunks[c0 + v];
+                d.tp += fbase;
+                d.s += fbase;
+                d.pbase += pb;
+                d.item0 = (int32_t)items;
+                d.block0 = j->next_block[u];
+                if (v == 0) {
+                    ChunkDesc l = d;
+                    l.n = src.n * cnt;
+                    leaders.push_back(l);
+                }
+                tab.push_back(d);
+            }
             starts.push_back((int32_t)items);
             items += take;
             pairs += (int64_t)take * per_block;
-            j->next_block[c] += take;
-            if (j->next_block[c] >= nb)
+            j->next_block[u] += take;
+            if (j->next_block[u] >= nb)
                 j->next_chunk++;
         }
-        if (j->next_chunk >= b.chunks.size()) {
+        if (j->next_chunk >= n_units) {
             j->all_scheduled = true;
             finishing.push_back(j);
         }
-        if ((pairs >= step_pairs && items >= min_items) || items >= max_items)
+        if ((pairs >= step_pairs && items >= min_items) || items >= max_items ||
+            (int64_t)tab.size() + kc.set_v > max_items)
             break;
     }
     if (tab.empty())
@@ -494,15 +553,21 @@ bool Server::issue_step(int ci)
         steps.push_back(st);
         return true;
     }
-    // step table into the class's slot: pieces, their first items, XCD queue bounds, queue heads
+    // step table into the class's slot: descriptors, the pieces' first items, their
+    // descriptor ranges (set classes), XCD queue bounds, queue heads
     std::vector<int32_t> qb;
-    queue_bounds(tab, items, &qb);
+    queue_bounds(leaders, items, &qb);
+    if (kc.sets)
+        sfirst.push_back((int32_t)tab.size());
     const size_t o_starts = align_up(sizeof(ChunkDesc) * tab.size(), 16);
-    const size_t o_qb = o_starts + align_up(sizeof(int32_t) * starts.size(), 16);
+    const size_t o_sets = o_starts + align_up(sizeof(int32_t) * starts.size(), 16);
+    const size_t o_qb = o_sets + align_up(sizeof(int32_t) * sfirst.size(), 16);
     const size_t tb = o_qb + sizeof(int32_t) * qb.size();
     char *h = static_cast<char *>(kc.stage[slot]);
     std::memcpy(h, tab.data(), sizeof(ChunkDesc) * tab.size());
     std::memcpy(h + o_starts, starts.data(), sizeof(int32_t) * starts.size());
+    if (!sfirst.empty())
+        std::memcpy(h + o_sets, sfirst.data(), sizeof(int32_t) * sfirst.size());
     std::memcpy(h + o_qb, qb.data(), sizeof(int32_t) * qb.size());
     char *dtab = arena + kc.table_off[slot];
     hipStream_t sm = kc.stream[slot];
@@ -516,7 +581,8 @@ bool Server::issue_step(int ci)
     a.item_start = reinterpret_cast<const int32_t *>(dtab + o_starts);
     a.n_parts = kQueues;
     a.part_start = reinterpret_cast<const int32_t *>(dtab + o_qb);
-    a.n_chunks = (int32_t)tab.size();
+    a.n_chunks = (int32_t)starts.size();
+    a.set_first = kc.sets ? reinterpret_cast<const int32_t *>(dtab + o_sets) : nullptr;
     a.n_items = (int32_t)items;
     a.k = kc.k;
     a.counter = ctr;
@@ -798,9 +864,19 @@ te_status te_serve_submit(te_server srv, const te_problem *problem, const float 
     j->t_submit = now_s();
     if (S.t_first == 0)
         S.t_first = j->t_submit;
-    j->cls = S.class_of(P.p, P.sorted);
-    if (j->cls < 0)
-        return reject(TE_ERR_NOMEM, "the arena cannot hold the step tables of a new kernel class");
+    j->cls = S.class_of(P.p, P.sorted, P.full.use_sets, P.full.set_v);
+    {
+        // the job, with its class's step tables, must fit beside the tables of every other
+        // class: they stay allocated once a job of theirs is admitted, and a class with jobs
+        // queued ahead of this one will be before it is
+        size_t others = 0;
+        for (size_t c = 0; c < S.classes.size(); ++c)
+            if ((int)c != j->cls)
+                others += 2 * align_up(S.classes[c].table_cap, 256);
+        const size_t own = 2 * align_up(S.classes[j->cls].table_cap, 256);
+        if (align_up(j->footprint, 256) + own + others > S.alloc.size)
+            return reject(TE_ERR_NOMEM, "the job and the step tables of its kernel class cannot fit the arena");
+    }
     *ticket = j->id;
     S.queue.push_back(j.get());
     S.jobs[j->id] = std::move(j);

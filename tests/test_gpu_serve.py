@@ -118,15 +118,15 @@ def test_invalid_job_fails_alone(te):
 
 def test_chunks_split_across_steps_match_alone(te, monkeypatch):
     """With one wave per CU a step holds 4 to 16 items per CU (1 024 to 4 096 items on 256 CUs),
-    so the four chunks of 40 000 points (625 blocks each, 2 500 items) are spread over at least
-    three steps in pieces; each piece is searched over its own blocks only and the results equal
-    the jobs run alone."""
+    so the two jobs' chunk sets of 80 000 points (an original and a surrogate each, 1 250 blocks,
+    2 500 items) are spread over at least three steps in pieces; each piece is searched over its
+    own blocks only and the results equal the jobs run alone."""
     monkeypatch.setenv("TE_WAVES_PER_WG", "1")
     monkeypatch.setenv("TE_WG_PER_CU", "1")
     jobs = []
     for i in range(2):
         h = synth.history(2, 2, 1, 1)
-        jobs.append(synth.generic((9200, i), R=2000, T=h + 25, d_y=2, d_x=2, starts=(h + 3,), windows=(20,),
+        jobs.append(synth.generic((9200, i), R=4000, T=h + 25, d_y=2, d_x=2, starts=(h + 3,), windows=(20,),
                                   n_surrogates=1))
     alone = [_alone(te, wl) for wl in jobs]
     srv = te.Server(arena_bytes=512 << 20, max_slots=2, step_pairs=1)

@@ -110,3 +110,24 @@ def test_failed_staging_releases_the_job_and_the_queue_moves_on(te, monkeypatch)
     srv.close()
     assert outcomes.count(2) == 1 and outcomes.count("ok") == 4, outcomes
     assert st["completed"] == 4 and st["failed"] == 1 and st["resident"] == 0 and st["queued"] == 0
+
+
+def test_mixed_classes_in_a_tight_arena_all_complete(te):
+    """Jobs of five kernel classes (dimensions, with and without surrogates) through an arena
+    just large enough for the classes' step tables and the largest job: class tables are
+    taken from the top of the arena, so job regions never fragment around them and every
+    job is admitted in turn."""
+    jobs = [_job(50 + i, R=R, S=S, d=d) for i, (R, S, d) in
+            enumerate([(30, 4, 2), (45, 2, 3), (25, 6, 4), (60, 0, 2), (20, 3, 3), (35, 1, 4), (50, 0, 3)])]
+    probe = te.Server(arena_bytes=1 << 30, max_slots=1, dry_run=True)
+    for t in [probe.submit(wl) for wl in jobs]:
+        probe.wait(t, timeout_s=30)
+    need = probe.stats()["peak_bytes"]
+    probe.close()
+    srv = te.Server(arena_bytes=need + (64 << 10), max_slots=8, dry_run=True)
+    tickets = [srv.submit(wl) for wl in jobs]
+    for t in tickets:
+        srv.wait(t, timeout_s=30)
+    st = srv.stats()
+    assert st["completed"] == len(jobs) and st["peak_bytes"] <= need + (64 << 10)
+    srv.close()

@@ -75,6 +75,10 @@ __device__ __forceinline__ void keep_branch() { asm volatile("" ::: "memory"); }
 
 constexpr float kInf = __builtin_inff();
 
+// Sorted chunks of at least this many points walk pass 1 outward from the reference
+// block in tiles (lane = candidate); smaller ones in groups (lane = reference).
+constexpr int kTileScanMin = 8192;
+
 __device__ __forceinline__ float absdiff(float a, float b) { return __builtin_fabsf(a - b); }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
@@ -393,7 +397,8 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
         // distance to candidate j is at least |fl32(p0_i - p0_j)|, which grows
         // monotonically away from the reference block (rounding is monotone).
 
-        int visited = n;                                  // candidates examined in pass 1
+        // (reference, candidate) pairs examined in pass 1
+        unsigned long long pass1_pairs = (unsigned long long)n * (unsigned long long)min(kWave, n - r0);
         int scan_lo = 0, scan_hi = n;                     // pass 1 examined [scan_lo, scan_hi)
         if (!SORTED) {
             int j = 0;
@@ -414,57 +419,188 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                 visit4(j);
             for (; j < e0; ++j)
                 visit1(j);
-            // then outward: forward (p0 increasing), then backward, a group of eight
-            // (four for wide rows, then four for the remainder) at a time.  After
-            // each group, its candidate farthest from the block is tested: if no
-            // lane could still use it, no later candidate of that direction could
-            // either (so the next group is not loaded).  All loads of a group feed
-            // its distances unconditionally: one wait per group.
-            int f = e0;
-            bool go = f < n;
-            while (kGroup8 && go && f + 8 <= n) {
-                float c[8][D];
-                load8(f, c);
-                visit_group8(c);
-                f += 8;
-                go = f < n && ballot(absdiff(ref[1], c[7][1]) < cur()) != 0;
+            // Outward from the block: for chunks of at least kTileScanMin points in tiles of
+            // 64 x TS candidates against the references whose windows reach them, below
+            // that in groups of candidates against all 64 references (where a chunk is
+            // small, the 64 windows nearly coincide and the groups' scalar loads cost less).
+            int f, b;
+            unsigned long long ev = (unsigned long long)(e0 - r0) * (unsigned long long)min(kWave, n - r0);
+            if (n >= kTileScanMin) {
+                // Then outward in tiles of 64 candidates, one per lane, alternating forward
+                // (p0 increasing) and backward: a tile is compared only with the references
+                // whose p0 window [p0 - r, p0 + r] (r their current (k+1)-th distance) reaches
+                // the tile's p0 span, read back as LDS broadcasts; a candidate below a
+                // reference's current (k+1)-th distance is moved to the reference's lane and
+                // inserted there.  A direction ends at the first tile that no reference
+                // reaches: every later candidate on that side is farther in p0.
+                // LDS row of a reference: its coordinates, then its current (k+1)-th distance
+                float *prow = rows + (threadIdx.x / kWave) * (kWave * RW);
+                __builtin_amdgcn_wave_barrier();
+    #pragma unroll
+                for (int m = 0; m < D; ++m)
+                    prow[lane * RW + m] = ref[m];
+                prow[lane * RW + D] = cur();
+                __builtin_amdgcn_wave_barrier();
+                constexpr int TS = 2;                        // a tile: 64 x TS candidates
+                auto read_row = [&](int r, float (&rr)[RW]) {
+                    const f4v *rowv = reinterpret_cast<const f4v *>(prow + r * RW);
+    #pragma unroll
+                    for (int x = 0; x < RW / 4; ++x) {
+                        const f4v q4 = rowv[x];
+                        rr[4 * x + 0] = q4.x;
+                        rr[4 * x + 1] = q4.y;
+                        rr[4 * x + 2] = q4.z;
+                        rr[4 * x + 3] = q4.w;
+                    }
+                };
+                auto tile = [&](int t0, int t1) {
+                    float cand[TS][D];
+    #pragma unroll
+                    for (int sl = 0; sl < TS; ++sl) {
+                        const int idx = t0 + sl * kWave + lane;
+                        const bool ok = idx < t1;
+    #pragma unroll
+                        for (int m = 0; m < D; ++m) {
+                            const float v = cp.p[m][ok ? idx : t0];
+                            cand[sl][m] = ok ? v : kInf;
+                        }
+                    }
+                    const float tlo = uload(cp.p[1] + t0), thi = uload(cp.p[1] + t1 - 1);
+                    const float c0 = cur();
+                    uint64_t todo = ballot(valid && !(tlo - ref[1] >= c0 || ref[1] - thi >= c0));
+                    ev += (unsigned long long)__builtin_popcountll(todo) * (unsigned long long)(t1 - t0);
+                    // the candidates of the tile against reference r (row rr), in the reference's lane
+                    auto against = [&](int r, const float (&rr)[RW]) {
+                        float ut = rr[D];
+    #pragma unroll
+                        for (int sl = 0; sl < TS; ++sl) {
+                            const PairDist<DY, DX> d = pair_dist_row<DY, DX, RW>(rr, cand[sl]);
+                            const float dj = fmaxf(d.t, fmaxf(d.p, d.s));
+                            uint64_t hit = ballot(dj < ut);
+                            while (hit != 0) {
+                                keep_branch();
+                                const int c = __builtin_ctzll(hit);
+                                const float x =
+                                    __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, dj), c));
+                                if (lane == r) {
+                                    insert_sorted<KP1>(best, x);
+                                    if (GENERIC)
+                                        thr = kth<KP1, GENERIC>(best, k);
+                                    prow[r * RW + D] = cur();
+                                }
+                                ut = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, cur()), r));
+                                hit &= hit - 1;
+                                hit &= ballot(dj < ut);
+                            }
+                        }
+                    };
+                    // two row buffers used in turn: the next reference's row is read while the
+                    // current one is compared (rows of different references: an insertion
+                    // rewrites only its own reference's row)
+                    if (todo != 0) {
+                        float ra[RW], rb[RW];
+                        int ia = __builtin_ctzll(todo);
+                        todo &= todo - 1;
+                        read_row(ia, ra);
+                        for (;;) {
+                            const bool mb = todo != 0;
+                            int ib = ia;
+                            if (mb) {
+                                ib = __builtin_ctzll(todo);
+                                todo &= todo - 1;
+                                read_row(ib, rb);
+                            }
+                            __builtin_amdgcn_sched_barrier(0);
+                            against(ia, ra);
+                            if (!mb)
+                                break;
+                            const bool mc = todo != 0;
+                            int ic = ib;
+                            if (mc) {
+                                ic = __builtin_ctzll(todo);
+                                todo &= todo - 1;
+                                read_row(ic, ra);
+                            }
+                            __builtin_amdgcn_sched_barrier(0);
+                            against(ib, rb);
+                            if (!mc)
+                                break;
+                            ia = ic;
+                        }
+                    }
+                };
+                f = e0;
+                b = r0;
+                bool fgo = f < n && ballot(valid && absdiff(ref[1], uload(cp.p[1] + f)) < cur()) != 0;
+                bool bgo = b > 0 && ballot(valid && absdiff(ref[1], uload(cp.p[1] + b - 1)) < cur()) != 0;
+                while (fgo || bgo) {
+                    if (fgo) {
+                        const int t1 = min(n, f + kWave * TS);
+                        tile(f, t1);
+                        f = t1;
+                        fgo = f < n && ballot(valid && absdiff(ref[1], uload(cp.p[1] + f)) < cur()) != 0;
+                    }
+                    if (bgo) {
+                        const int t0 = max(0, b - kWave * TS);
+                        tile(t0, b);
+                        b = t0;
+                        bgo = b > 0 && ballot(valid && absdiff(ref[1], uload(cp.p[1] + b - 1)) < cur()) != 0;
+                    }
+                }
+            } else {
+                // then outward: forward (p0 increasing), then backward, a group of eight
+                // (four for wide rows, then four for the remainder) at a time.  After
+                // each group, its candidate farthest from the block is tested: if no
+                // lane could still use it, no later candidate of that direction could
+                // either (so the next group is not loaded).  All loads of a group feed
+                // its distances unconditionally: one wait per group.
+                f = e0;
+                bool go = f < n;
+                while (kGroup8 && go && f + 8 <= n) {
+                    float c[8][D];
+                    load8(f, c);
+                    visit_group8(c);
+                    f += 8;
+                    go = f < n && ballot(absdiff(ref[1], c[7][1]) < cur()) != 0;
+                }
+                while (go && f + 4 <= n) {
+                    float c[4][D];
+                    load4(f, c);
+                    visit_group(c);
+                    f += 4;
+                    go = f < n && ballot(absdiff(ref[1], c[3][1]) < cur()) != 0;
+                }
+                while (go && f < n) {
+                    const float p0 = uload(cp.p[1] + f);
+                    visit1(f);
+                    ++f;
+                    go = f < n && ballot(absdiff(ref[1], p0) < cur()) != 0;
+                }
+                b = r0;
+                go = b > 0;
+                while (kGroup8 && go && b >= 8) {
+                    float c[8][D];
+                    load8(b - 8, c);
+                    visit_group8(c);
+                    b -= 8;
+                    go = b > 0 && ballot(absdiff(ref[1], c[0][1]) < cur()) != 0;
+                }
+                while (go && b >= 4) {
+                    float c[4][D];
+                    load4(b - 4, c);
+                    visit_group(c);
+                    b -= 4;
+                    go = b > 0 && ballot(absdiff(ref[1], c[0][1]) < cur()) != 0;
+                }
+                while (go && b > 0) {
+                    const float p0 = uload(cp.p[1] + b - 1);
+                    visit1(b - 1);
+                    --b;
+                    go = b > 0 && ballot(absdiff(ref[1], p0) < cur()) != 0;
+                }
+                ev = (unsigned long long)(f - b) * (unsigned long long)min(kWave, n - r0);
             }
-            while (go && f + 4 <= n) {
-                float c[4][D];
-                load4(f, c);
-                visit_group(c);
-                f += 4;
-                go = f < n && ballot(absdiff(ref[1], c[3][1]) < cur()) != 0;
-            }
-            while (go && f < n) {
-                const float p0 = uload(cp.p[1] + f);
-                visit1(f);
-                ++f;
-                go = f < n && ballot(absdiff(ref[1], p0) < cur()) != 0;
-            }
-            int b = r0;
-            go = b > 0;
-            while (kGroup8 && go && b >= 8) {
-                float c[8][D];
-                load8(b - 8, c);
-                visit_group8(c);
-                b -= 8;
-                go = b > 0 && ballot(absdiff(ref[1], c[0][1]) < cur()) != 0;
-            }
-            while (go && b >= 4) {
-                float c[4][D];
-                load4(b - 4, c);
-                visit_group(c);
-                b -= 4;
-                go = b > 0 && ballot(absdiff(ref[1], c[0][1]) < cur()) != 0;
-            }
-            while (go && b > 0) {
-                const float p0 = uload(cp.p[1] + b - 1);
-                visit1(b - 1);
-                --b;
-                go = b > 0 && ballot(absdiff(ref[1], p0) < cur()) != 0;
-            }
-            visited = f - b;
+            pass1_pairs = ev;
             scan_lo = b;
             scan_hi = f;
         }
@@ -630,7 +766,7 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
         const double sum = wave_sum(term);
         if (lane == 0)
             a.partial[cd.pbase + blk] = sum;
-        work1 += (unsigned long long)visited * (unsigned long long)nref;
+        work1 += pass1_pairs;
         work2 += evaluated2;
         if (a.lte_out != nullptr && cd.out >= 0 && valid) {
             int o = (cd.perm >= 0) ? a.perm_base[cd.perm + i] : i;
@@ -865,37 +1001,149 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_sets_kernel(Search
         }
         for (; j < e0; ++j)
             visit1(j);
-        int f = e0;
-        bool go = f < n;
-        while (go && f + 4 <= n) {
-            float ct[4][DT], cs[V][4][DX];
-            load4(f, ct, cs);
-            visit4(ct, cs);
-            f += 4;
-            go = f < n && ballot(absdiff(rt[1], ct[3][1]) < curmax()) != 0;
+        // Outward from the block: for chunks of at least kTileScanMin points in tiles of 64
+        // candidates against the references whose windows reach them, below that in groups
+        // of four candidates against all 64 references.
+        int f, b;
+        unsigned long long ev = (unsigned long long)(e0 - r0) * (unsigned long long)min(kWave, n - r0);
+        if (n >= kTileScanMin) {
+            // then outward in tiles of 64 candidates (lane = candidate), alternating forward and
+            // backward, each compared only with the references whose p0 window at their largest
+            // current radius reaches the tile; the LDS row of a reference holds its coordinates
+            // and its current (k+1)-th distance per variant
+            float *prow = rows + (threadIdx.x / kWave) * (kWave * RW);
+            __builtin_amdgcn_wave_barrier();
+    #pragma unroll
+            for (int m = 0; m < DT; ++m)
+                prow[lane * RW + m] = rt[m];
+    #pragma unroll
+            for (int v = 0; v < V; ++v) {
+    #pragma unroll
+                for (int m = 0; m < DX; ++m)
+                    prow[lane * RW + DT + v * DX + m] = rs[v][m];
+                prow[lane * RW + DT + V * DX + v] = best[v][KP1 - 1];
+            }
+            __builtin_amdgcn_wave_barrier();
+            auto read_row = [&](int r, float (&rr)[RW]) {
+                const f4v *rowv = reinterpret_cast<const f4v *>(prow + r * RW);
+    #pragma unroll
+                for (int x = 0; x < RW / 4; ++x) {
+                    const f4v q4 = rowv[x];
+                    rr[4 * x + 0] = q4.x;
+                    rr[4 * x + 1] = q4.y;
+                    rr[4 * x + 2] = q4.z;
+                    rr[4 * x + 3] = q4.w;
+                }
+            };
+            auto tile = [&](int t0, int t1) {
+                const int idx = t0 + lane;
+                const bool ok = idx < t1;
+                const int ic = ok ? idx : t0;
+                float ct[DT], cs[V][DX];
+    #pragma unroll
+                for (int m = 0; m < DT; ++m) {
+                    const float x = tb[(int64_t)m * ld + ic];
+                    ct[m] = ok ? x : kInf;
+                }
+    #pragma unroll
+                for (int v = 0; v < V; ++v)
+    #pragma unroll
+                    for (int m = 0; m < DX; ++m) {
+                        const float x = sb[v][(int64_t)m * ld + ic];
+                        cs[v][m] = ok ? x : kInf;
+                    }
+                const float tlo = uload(tb + ld + t0), thi = uload(tb + ld + t1 - 1);
+                const float c0 = curmax();
+                uint64_t todo = ballot(valid && !(tlo - rt[1] >= c0 || rt[1] - thi >= c0));
+                ev += (unsigned long long)__builtin_popcountll(todo) * (unsigned long long)(t1 - t0);
+                auto against = [&](int r, const float (&rr)[RW]) {
+                    float dtp = absdiff(rr[0], ct[0]);
+    #pragma unroll
+                    for (int m = 1; m < DT; ++m)
+                        dtp = fmaxf(dtp, absdiff(rr[m], ct[m]));
+    #pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        float d = absdiff(rr[DT + v * DX], cs[v][0]);
+    #pragma unroll
+                        for (int m = 1; m < DX; ++m)
+                            d = fmaxf(d, absdiff(rr[DT + v * DX + m], cs[v][m]));
+                        const float dj = fmaxf(dtp, d);
+                        float ut = rr[DT + V * DX + v];
+                        uint64_t hit = ballot(dj < ut);
+                        while (hit != 0) {
+                            keep_branch();
+                            const int c = __builtin_ctzll(hit);
+                            const float x =
+                                __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, dj), c));
+                            if (lane == r) {
+                                insert_sorted<KP1>(best[v], x);
+                                prow[r * RW + DT + V * DX + v] = best[v][KP1 - 1];
+                            }
+                            ut = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, best[v][KP1 - 1]), r));
+                            hit &= hit - 1;
+                            hit &= ballot(dj < ut);
+                        }
+                    }
+                };
+                while (todo != 0) {
+                    const int r = __builtin_ctzll(todo);
+                    todo &= todo - 1;
+                    float rr[RW];
+                    read_row(r, rr);
+                    against(r, rr);
+                }
+            };
+            f = e0;
+            b = r0;
+            bool fgo = f < n && ballot(valid && absdiff(rt[1], uload(tb + ld + f)) < curmax()) != 0;
+            bool bgo = b > 0 && ballot(valid && absdiff(rt[1], uload(tb + ld + b - 1)) < curmax()) != 0;
+            while (fgo || bgo) {
+                if (fgo) {
+                    const int t1 = min(n, f + kWave);
+                    tile(f, t1);
+                    f = t1;
+                    fgo = f < n && ballot(valid && absdiff(rt[1], uload(tb + ld + f)) < curmax()) != 0;
+                }
+                if (bgo) {
+                    const int t0 = max(0, b - kWave);
+                    tile(t0, b);
+                    b = t0;
+                    bgo = b > 0 && ballot(valid && absdiff(rt[1], uload(tb + ld + b - 1)) < curmax()) != 0;
+                }
+            }
+        } else {
+            f = e0;
+            bool go = f < n;
+            while (go && f + 4 <= n) {
+                float ct[4][DT], cs[V][4][DX];
+                load4(f, ct, cs);
+                visit4(ct, cs);
+                f += 4;
+                go = f < n && ballot(absdiff(rt[1], ct[3][1]) < curmax()) != 0;
+            }
+            while (go && f < n) {
+                const float p0 = uload(tb + ld + f);
+                visit1(f);
+                ++f;
+                go = f < n && ballot(absdiff(rt[1], p0) < curmax()) != 0;
+            }
+            b = r0;
+            go = b > 0;
+            while (go && b >= 4) {
+                float ct[4][DT], cs[V][4][DX];
+                load4(b - 4, ct, cs);
+                visit4(ct, cs);
+                b -= 4;
+                go = b > 0 && ballot(absdiff(rt[1], ct[0][1]) < curmax()) != 0;
+            }
+            while (go && b > 0) {
+                const float p0 = uload(tb + ld + b - 1);
+                visit1(b - 1);
+                --b;
+                go = b > 0 && ballot(absdiff(rt[1], p0) < curmax()) != 0;
+            }
+            ev = (unsigned long long)(f - b) * (unsigned long long)min(kWave, n - r0);
         }
-        while (go && f < n) {
-            const float p0 = uload(tb + ld + f);
-            visit1(f);
-            ++f;
-            go = f < n && ballot(absdiff(rt[1], p0) < curmax()) != 0;
-        }
-        int b = r0;
-        go = b > 0;
-        while (go && b >= 4) {
-            float ct[4][DT], cs[V][4][DX];
-            load4(b - 4, ct, cs);
-            visit4(ct, cs);
-            b -= 4;
-            go = b > 0 && ballot(absdiff(rt[1], ct[0][1]) < curmax()) != 0;
-        }
-        while (go && b > 0) {
-            const float p0 = uload(tb + ld + b - 1);
-            visit1(b - 1);
-            --b;
-            go = b > 0 && ballot(absdiff(rt[1], p0) < curmax()) != 0;
-        }
-        const int visited = f - b;
         float eps[V];
 #pragma unroll
         for (int v = 0; v < V; ++v)
@@ -1027,9 +1275,9 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_sets_kernel(Search
             if (lane == 0 && v < cnt)
                 a.partial[pb[v] + blk] = sum;
         }
-        work1 += (unsigned long long)visited * (unsigned long long)nref * (unsigned long long)cnt;
+        work1 += ev * (unsigned long long)cnt;
         work2 += evaluated2 * (unsigned long long)cnt;
-        shared1 += (unsigned long long)visited * (unsigned long long)nref;
+        shared1 += ev;
         shared2 += evaluated2;
     }
     if (a.work != nullptr && lane == 0) {

@@ -76,7 +76,9 @@ def valu_ceiling(sub: float, mx: float, cmp: float) -> float:
 # HBM bytes per search launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs, scaled by a plain 256 MiB
 # device copy measured the same way (factors 2.000 and 1.000), keyed by (kernel source, workload); any other
 # kernel source reports null.
-RECORDED_TRAFFIC = {}
+RECORDED_TRAFFIC = {
+    ("65509c3e288c", "uneven_chunks_200_surrogates"): 75001758272,
+}
 KERNEL_SRC = os.path.join(ROOT, "paper_1401_4068_amd", "csrc", "te_kernels.hip")
 
 

@@ -740,10 +740,27 @@ void Server::loop()
         }
         if (!dry)
             poll_setup();
+        // At most two steps in flight over all classes (the second covers the tail of the
+        // first); each new step goes to the class of the oldest resident job with blocks left
+        // to schedule, so jobs progress in admission order across classes as within one and a
+        // job is not slowed by younger jobs of other classes sharing the GPU.
         bool issued = false;
-        for (size_t ci = 0; ci < classes.size(); ++ci)
-            if (classes[ci].in_flight < 2)
-                issued |= issue_step((int)ci);
+        for (;;) {
+            int total = 0;
+            for (const KernelClass &c : classes)
+                total += c.in_flight;
+            if (total >= 2)
+                break;
+            int ci = -1;
+            for (Job *j : resident)
+                if (j->state == READY && !j->all_scheduled && classes[j->cls].in_flight < 2) {
+                    ci = j->cls;
+                    break;
+                }
+            if (ci < 0 || !issue_step(ci))
+                break;
+            issued = true;
+        }
         poll_steps();
         const bool busy = !steps.empty() || !queue.empty() ||
                           std::any_of(resident.begin(), resident.end(), [](Job *j) { return j->state == SETUP; });

@@ -78,6 +78,7 @@ def valu_ceiling(sub: float, mx: float, cmp: float) -> float:
 # kernel source reports null.
 RECORDED_TRAFFIC = {
     ("65509c3e288c", "uneven_chunks_200_surrogates"): 75001758272,
+    ("65509c3e288c", "nonlinear_ar_ensemble"): 18894977,
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_1401_4068_amd", "csrc", "te_kernels.hip")
 
@@ -315,7 +316,8 @@ def batched_record(args, wl, wname):
     est = wl.n_estimates()
     value = est * args.steps / dt
     evals_per_s = 2 * pairs_per_pass * args.steps / dt
-    slots = tuned["slots"] if tuned else 4
+    env_slots = os.environ.get("TE_SLOTS", "")
+    slots = tuned["slots"] if tuned else (int(env_slots) if env_slots.isdigit() else 4)
     roof = None
     if k_n > 0:
         roof = roofline_record(wl, wname, k_ms, k_n, work, 1, slots, pairs_per_pass * args.steps / k_n)

@@ -436,7 +436,7 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                 // LDS row of a reference: its coordinates, then its current (k+1)-th distance
                 float *prow = rows + (threadIdx.x / kWave) * (kWave * RW);
                 __builtin_amdgcn_wave_barrier();
-    #pragma unroll
+#pragma unroll
                 for (int m = 0; m < D; ++m)
                     prow[lane * RW + m] = ref[m];
                 prow[lane * RW + D] = cur();
@@ -444,7 +444,7 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                 constexpr int TS = 2;                        // a tile: 64 x TS candidates
                 auto read_row = [&](int r, float (&rr)[RW]) {
                     const f4v *rowv = reinterpret_cast<const f4v *>(prow + r * RW);
-    #pragma unroll
+#pragma unroll
                     for (int x = 0; x < RW / 4; ++x) {
                         const f4v q4 = rowv[x];
                         rr[4 * x + 0] = q4.x;
@@ -455,11 +455,11 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                 };
                 auto tile = [&](int t0, int t1) {
                     float cand[TS][D];
-    #pragma unroll
+#pragma unroll
                     for (int sl = 0; sl < TS; ++sl) {
                         const int idx = t0 + sl * kWave + lane;
                         const bool ok = idx < t1;
-    #pragma unroll
+#pragma unroll
                         for (int m = 0; m < D; ++m) {
                             const float v = cp.p[m][ok ? idx : t0];
                             cand[sl][m] = ok ? v : kInf;
@@ -472,7 +472,7 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                     // the candidates of the tile against reference r (row rr), in the reference's lane
                     auto against = [&](int r, const float (&rr)[RW]) {
                         float ut = rr[D];
-    #pragma unroll
+#pragma unroll
                         for (int sl = 0; sl < TS; ++sl) {
                             const PairDist<DY, DX> d = pair_dist_row<DY, DX, RW>(rr, cand[sl]);
                             const float dj = fmaxf(d.t, fmaxf(d.p, d.s));
@@ -1013,12 +1013,12 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_sets_kernel(Search
             // and its current (k+1)-th distance per variant
             float *prow = rows + (threadIdx.x / kWave) * (kWave * RW);
             __builtin_amdgcn_wave_barrier();
-    #pragma unroll
+#pragma unroll
             for (int m = 0; m < DT; ++m)
                 prow[lane * RW + m] = rt[m];
-    #pragma unroll
+#pragma unroll
             for (int v = 0; v < V; ++v) {
-    #pragma unroll
+#pragma unroll
                 for (int m = 0; m < DX; ++m)
                     prow[lane * RW + DT + v * DX + m] = rs[v][m];
                 prow[lane * RW + DT + V * DX + v] = best[v][KP1 - 1];
@@ -1026,7 +1026,7 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_sets_kernel(Search
             __builtin_amdgcn_wave_barrier();
             auto read_row = [&](int r, float (&rr)[RW]) {
                 const f4v *rowv = reinterpret_cast<const f4v *>(prow + r * RW);
-    #pragma unroll
+#pragma unroll
                 for (int x = 0; x < RW / 4; ++x) {
                     const f4v q4 = rowv[x];
                     rr[4 * x + 0] = q4.x;
@@ -1035,53 +1035,78 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_sets_kernel(Search
                     rr[4 * x + 3] = q4.w;
                 }
             };
+            // a tile: 64 x TS candidates; two slots only where their coordinates stay few (the
+            // candidate registers of a second slot would otherwise cost a wave per SIMD)
+            constexpr int TS = (DT + V * DX <= 8) ? 2 : 1;
             auto tile = [&](int t0, int t1) {
-                const int idx = t0 + lane;
-                const bool ok = idx < t1;
-                const int ic = ok ? idx : t0;
-                float ct[DT], cs[V][DX];
-    #pragma unroll
-                for (int m = 0; m < DT; ++m) {
-                    const float x = tb[(int64_t)m * ld + ic];
-                    ct[m] = ok ? x : kInf;
-                }
-    #pragma unroll
-                for (int v = 0; v < V; ++v)
-    #pragma unroll
-                    for (int m = 0; m < DX; ++m) {
-                        const float x = sb[v][(int64_t)m * ld + ic];
-                        cs[v][m] = ok ? x : kInf;
+                float ct[TS][DT], cs[TS][V][DX];
+#pragma unroll
+                for (int sl = 0; sl < TS; ++sl) {
+                    const int idx = t0 + sl * kWave + lane;
+                    const bool ok = idx < t1;
+                    const int ic = ok ? idx : t0;
+#pragma unroll
+                    for (int m = 0; m < DT; ++m) {
+                        const float x = tb[(int64_t)m * ld + ic];
+                        ct[sl][m] = ok ? x : kInf;
                     }
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+#pragma unroll
+                        for (int m = 0; m < DX; ++m) {
+                            const float x = sb[v][(int64_t)m * ld + ic];
+                            cs[sl][v][m] = ok ? x : kInf;
+                        }
+                }
                 const float tlo = uload(tb + ld + t0), thi = uload(tb + ld + t1 - 1);
                 const float c0 = curmax();
                 uint64_t todo = ballot(valid && !(tlo - rt[1] >= c0 || rt[1] - thi >= c0));
                 ev += (unsigned long long)__builtin_popcountll(todo) * (unsigned long long)(t1 - t0);
+                // the tile against reference r (row rr): one branch per slot when no variant of the
+                // reference improves, which is the common case once its lists have settled
                 auto against = [&](int r, const float (&rr)[RW]) {
-                    float dtp = absdiff(rr[0], ct[0]);
-    #pragma unroll
-                    for (int m = 1; m < DT; ++m)
-                        dtp = fmaxf(dtp, absdiff(rr[m], ct[m]));
-    #pragma unroll
-                    for (int v = 0; v < V; ++v) {
-                        float d = absdiff(rr[DT + v * DX], cs[v][0]);
-    #pragma unroll
-                        for (int m = 1; m < DX; ++m)
-                            d = fmaxf(d, absdiff(rr[DT + v * DX + m], cs[v][m]));
-                        const float dj = fmaxf(dtp, d);
-                        float ut = rr[DT + V * DX + v];
-                        uint64_t hit = ballot(dj < ut);
-                        while (hit != 0) {
-                            keep_branch();
-                            const int c = __builtin_ctzll(hit);
-                            const float x =
-                                __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, dj), c));
-                            if (lane == r) {
-                                insert_sorted<KP1>(best[v], x);
-                                prow[r * RW + DT + V * DX + v] = best[v][KP1 - 1];
+                    float ut[V];
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+                        ut[v] = rr[DT + V * DX + v];
+#pragma unroll
+                    for (int sl = 0; sl < TS; ++sl) {
+                        float dtp = absdiff(rr[0], ct[sl][0]);
+#pragma unroll
+                        for (int m = 1; m < DT; ++m)
+                            dtp = fmaxf(dtp, absdiff(rr[m], ct[sl][m]));
+                        float dj[V];
+                        uint64_t hm[V], any = 0;
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            float d = absdiff(rr[DT + v * DX], cs[sl][v][0]);
+#pragma unroll
+                            for (int m = 1; m < DX; ++m)
+                                d = fmaxf(d, absdiff(rr[DT + v * DX + m], cs[sl][v][m]));
+                            dj[v] = fmaxf(dtp, d);
+                            hm[v] = ballot(dj[v] < ut[v]);
+                            any |= hm[v];
+                        }
+                        if (any == 0)
+                            continue;
+                        keep_branch();
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            uint64_t hit = hm[v];
+                            while (hit != 0) {
+                                keep_branch();
+                                const int c = __builtin_ctzll(hit);
+                                const float x = __builtin_bit_cast(
+                                    float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, dj[v]), c));
+                                if (lane == r) {
+                                    insert_sorted<KP1>(best[v], x);
+                                    prow[r * RW + DT + V * DX + v] = best[v][KP1 - 1];
+                                }
+                                ut[v] = __builtin_bit_cast(
+                                    float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, best[v][KP1 - 1]), r));
+                                hit &= hit - 1;
+                                hit &= ballot(dj[v] < ut[v]);
                             }
-                            ut = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, best[v][KP1 - 1]), r));
-                            hit &= hit - 1;
-                            hit &= ballot(dj < ut);
                         }
                     }
                 };
@@ -1099,13 +1124,13 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_sets_kernel(Search
             bool bgo = b > 0 && ballot(valid && absdiff(rt[1], uload(tb + ld + b - 1)) < curmax()) != 0;
             while (fgo || bgo) {
                 if (fgo) {
-                    const int t1 = min(n, f + kWave);
+                    const int t1 = min(n, f + kWave * TS);
                     tile(f, t1);
                     f = t1;
                     fgo = f < n && ballot(valid && absdiff(rt[1], uload(tb + ld + f)) < curmax()) != 0;
                 }
                 if (bgo) {
-                    const int t0 = max(0, b - kWave);
+                    const int t0 = max(0, b - kWave * TS);
                     tile(t0, b);
                     b = t0;
                     bgo = b > 0 && ballot(valid && absdiff(rt[1], uload(tb + ld + b - 1)) < curmax()) != 0;

@@ -203,6 +203,14 @@ def make_workload(name):
     raise SystemExit("unknown workload " + name)
 
 
+def set_kernel_name(d_y: int, d_x: int) -> str:
+    """Name of the library's chunk-set search kernel for these dimensions: sets of as many chunks (2-4) as keep
+    4 (1 + d_y + V d_x) coordinates within 64 scalar registers; the wide form for 1 + d_y + V d_x >= 16."""
+    q = (15 - d_y) // d_x
+    v = 4 if q >= 4 else (2 if q <= 2 else q)
+    return "sets_wide_kernel" if 1 + d_y + v * d_x >= 16 else "sets_kernel"
+
+
 def roofline_record(wl, wname, k_ms, k_n, w, work_launches, slots, pairs_per_pass_step):
     """The search kernel on the FP32 VALU roofline.  achieved = FP32 ops the launch executed (device
     work counters of an untimed step, see executed_ops) / the average launch duration of the timed
@@ -223,8 +231,8 @@ def roofline_record(wl, wname, k_ms, k_n, w, work_launches, slots, pairs_per_pas
         peak_derivation="78.64e12 FP32 lane-instr/s (256 CU x 4 SIMD x 32 lanes x 2.4 GHz) x executed ops per "
                         "instruction of their fewest-instruction form (%.3g sub + %.3g max + %.3g cmp per launch; "
                         "sub and cmp one op per instruction, two maxes per v_max3; no packed FP32)" % (sub, mx, cmp),
-        kernel="search_%s<%d,%d,k=%d,slots=%d,sorted>" % ("sets_kernel" if w[2] < w[0] else "kernel", DT - 1, DX,
-                                                           wl.k, slots),
+        kernel="search_%s<%d,%d,k=%d,slots=%d,sorted>" % (set_kernel_name(DT - 1, DX) if w[2] < w[0] else "kernel",
+                                                           DT - 1, DX, wl.k, slots),
         kernel_src=kernel_sha(), avg_launch_ms=round(avg_s * 1e3, 4), launches=k_n,
         pairs_evaluated_per_launch=[int(w[0]), int(w[1])], shared_pairs_per_launch=[int(w[2]), int(w[3])],
         ops_per_launch=int(ops), method_pairs_per_launch=int(pairs_per_pass_step),

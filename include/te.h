@@ -115,7 +115,7 @@ const char *te_last_error(void);
 /* Validate a problem and precompute its geometry, chunk sizes and schedule.
  * TE_ERR_INVALID if a dimension is out of range, a window lacks history
  * (w_c < max(1+(d_y-1)tau, u+(d_x-1)tau)) or runs past n_samples, or a window
- * pools N_c = R_c W_c <= k points.  The plan is read-only afterwards and may be
+ * pools N_c = R_c W_c <= k points or more than 2^27 (134 217 728) points.  The plan is read-only afterwards and may be
  * used from several threads, each with its own workspace and stream. */
 te_status te_plan_create(const te_problem *problem, te_plan *out);
 te_status te_plan_destroy(te_plan plan);

@@ -601,8 +601,11 @@ te_status te_plan_create(const te_problem *pr, te_plan *out)
         const int64_t N = (int64_t)Rc * W;
         if (N <= p.k)
             return fail(TE_ERR_INVALID, "window %d pools %lld points, need more than k = %d", c, (long long)N, p.k);
-        if (N > (1 << 30))
-            return fail(TE_ERR_INVALID, "window %d pools too many points", c);
+        // the search kernels address a coordinate of a block by a 32-bit byte offset from
+        // the block's start (at most 5 rows of N floats before it): N <= 2^27 keeps it in range
+        if (N > kMaxWindowPoints)
+            return fail(TE_ERR_INVALID, "window %d pools %lld points, more than %d", c, (long long)N,
+                        kMaxWindowPoints);
         P.wstart.push_back(w);
         P.wlen.push_back(W);
         P.trials.push_back(Rc);

@@ -113,6 +113,10 @@ constexpr int set_variants(int d_y, int d_x)
 }
 constexpr int kMaxSetVariants = 4;
 
+// Points per window (pooled chunk) at most: the set search addresses coordinate m of a
+// block as a 32-bit byte offset 4 (m ld + j) from the block's start, m <= 4 and ld = N.
+constexpr int kMaxWindowPoints = 1 << 27;
+
 // Work queues of a batched search: one per XCD of an MI355X.  Workgroups are
 // dispatched to the XCDs round-robin, so the waves of workgroup g start on queue
 // g % kQueues and a chunk's coordinates stay in one XCD's L2; a wave whose queue

@@ -66,6 +66,7 @@ def test_plan_sizes_without_gpu():
     (dict(window_len=[0]), "length"),
     (dict(trials=[21]), "trials"),
     (dict(trials=[1], window_len=[4]), "need more than k"),     # N = 4 <= k
+    (dict(n_trials=1 << 14, n_samples=(1 << 14) + 10, window_len=[1 << 14]), "more than 134217728"),  # N = 2^28
     (dict(n_surrogates=-1), "n_surrogates"),
     (dict(window_start=[], window_len=None), "n_points"),        # no analysis window at all
 ])
@@ -75,6 +76,12 @@ def test_plan_rejects_invalid_geometry(bad, msg):
     with pytest.raises(TEError) as ei:
         _plan(**bad)
     assert ei.value.status == 1 and msg in str(ei.value)
+
+
+def test_plan_accepts_the_largest_window():
+    _lib_or_build()
+    p = _plan(n_trials=1 << 13, n_samples=(1 << 14) + 10, window_len=[1 << 14], n_surrogates=1)   # N = 2^27
+    assert p.workspace_bytes()[0] > 4 * 3 * (1 << 27)
 
 
 def test_history_rule_matches_embedding():

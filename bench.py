@@ -77,8 +77,8 @@ def valu_ceiling(sub: float, mx: float, cmp: float) -> float:
 # device copy measured the same way (factors 2.000 and 1.000), keyed by (kernel source, workload); any other
 # kernel source reports null.
 RECORDED_TRAFFIC = {
-    ("3219110b6a2f", "uneven_chunks_200_surrogates"): 257255006720,
-    ("3219110b6a2f", "nonlinear_ar_ensemble"): 19136736,
+    ("e2709849861a", "uneven_chunks_200_surrogates"): 171724200872,
+    ("e2709849861a", "nonlinear_ar_ensemble"): 19403050,
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_1401_4068_amd", "csrc", "te_kernels.hip")
 

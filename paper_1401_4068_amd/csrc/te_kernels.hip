@@ -66,6 +66,12 @@ __device__ __forceinline__ f4v uload4_at(const float *p, uint32_t byte_off)
     typedef const __attribute__((address_space(4))) char cchar_t;
     return *(cf4_t *)((cchar_t *)p + byte_off);
 }
+// per-lane load at a 32-bit byte offset from a wave-uniform base: the base stays in
+// SGPRs and the offset in one VGPR (no 64-bit address per lane)
+__device__ __forceinline__ float vload_at(const float *p, uint32_t byte_off)
+{
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(p) + byte_off);
+}
 __device__ __forceinline__ int32_t uload_i(const int32_t *p) { return *(cint_t *)p; }
 __device__ __forceinline__ int64_t uload_l(const int64_t *p) { return *(cint64_t *)p; }
 
@@ -459,9 +465,10 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
                     for (int sl = 0; sl < TS; ++sl) {
                         const int idx = t0 + sl * kWave + lane;
                         const bool ok = idx < t1;
+                        const uint32_t ic4 = (uint32_t)(ok ? idx : t0) * 4u;
 #pragma unroll
                         for (int m = 0; m < D; ++m) {
-                            const float v = cp.p[m][ok ? idx : t0];
+                            const float v = vload_at(cp.p[m], ic4);
                             cand[sl][m] = ok ? v : kInf;
                         }
                     }
@@ -645,10 +652,11 @@ __global__ void __launch_bounds__(kMaxWavesPerWG * 64) search_kernel(SearchArgs 
             for (int sl = 0; sl < SLOTS; ++sl) {
                 const int idx = t0 + sl * kWave + lane;
                 const bool ok = idx < hi;
-                const int ic = ok ? idx : n - 1;       // in-bounds load, lanes past the range masked below
+                // in-bounds load, lanes past the range masked below
+                const uint32_t ic4 = (uint32_t)(ok ? idx : n - 1) * 4u;
 #pragma unroll
                 for (int m = 0; m < D; ++m) {
-                    const float v = cp.p[m][ic];
+                    const float v = vload_at(cp.p[m], ic4);
                     cand[sl][m] = ok ? v : kInf;
                 }
             }
@@ -1046,17 +1054,17 @@ __device__ __forceinline__ void sets_search(const SearchArgs &a)
                 for (int sl = 0; sl < TS; ++sl) {
                     const int idx = t0 + sl * kWave + lane;
                     const bool ok = idx < t1;
-                    const int ic = ok ? idx : t0;
+                    const uint32_t ic4 = (uint32_t)(ok ? idx : t0) * 4u;
 #pragma unroll
                     for (int m = 0; m < DT; ++m) {
-                        const float x = tb[(int64_t)m * ld + ic];
+                        const float x = vload_at(tb, moff[m] + ic4);
                         ct[sl][m] = ok ? x : kInf;
                     }
 #pragma unroll
                     for (int v = 0; v < V; ++v)
 #pragma unroll
                         for (int m = 0; m < DX; ++m) {
-                            const float x = sb[v][(int64_t)m * ld + ic];
+                            const float x = vload_at(sb[v], moff[m] + ic4);
                             cs[sl][v][m] = ok ? x : kInf;
                         }
                 }
@@ -1213,17 +1221,17 @@ __device__ __forceinline__ void sets_search(const SearchArgs &a)
             for (int sl = 0; sl < SLOTS; ++sl) {
                 const int idx = t0 + sl * kWave + lane;
                 const bool ok = idx < hi;
-                const int ic = ok ? idx : n - 1;
+                const uint32_t ic4 = (uint32_t)(ok ? idx : n - 1) * 4u;
 #pragma unroll
                 for (int m = 0; m < DT; ++m) {
-                    const float x = tb[(int64_t)m * ld + ic];
+                    const float x = vload_at(tb, moff[m] + ic4);
                     ct[sl][m] = ok ? x : kInf;
                 }
 #pragma unroll
                 for (int v = 0; v < V; ++v)
 #pragma unroll
                     for (int m = 0; m < DX; ++m) {
-                        const float x = sb[v][(int64_t)m * ld + ic];
+                        const float x = vload_at(sb[v], moff[m] + ic4);
                         cs[sl][v][m] = ok ? x : kInf;
                     }
             }

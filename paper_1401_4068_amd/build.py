@@ -51,7 +51,7 @@ def build(verbose: bool = False, sanitize: str = "") -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(lambda s: _compile(s, objdir, extra), srcs))
     tmp = out + ".tmp%d" % os.getpid()
-    cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
+    cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread", "-lrocprofiler-sdk-roctx"]
     if sanitize:
         cmd += ["-Xarch_host", "-fsanitize=" + sanitize, "-shared-libsan"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -248,6 +248,7 @@ static int history(const te_problem &p)
 
 te_status Plan::build_group_batch(const std::vector<int> &groups, int n_surr, Batch *b, const BatchOptions &opt) const
 {
+    TraceRange trace_range("te.build_batch");
     if (opt.delays)
         n_surr = (int)opt.delays->size() - 1;
     // groups: indices g = pair * n_points + point; every group gets S+1 chunks
@@ -441,6 +442,7 @@ te_status Plan::enqueue_batch(const Batch &b, const float *x, const float *y, co
                               void *stage, hipStream_t st, double *lte_out, const int32_t *u_dev,
                               const void *tables_src, void *out_dst) const
 {
+    TraceRange trace_range("te.enqueue_batch");
     hipError_t e;
     char *tables_host = static_cast<char *>(stage);
     if (tables_src == nullptr) {
@@ -524,6 +526,7 @@ size_t Batch::stage_bytes() const
 te_status Plan::unpack_batch(const Batch &b, const void *stage, double *te_orig, double *te_surr, double *p_value,
                              bool *bad_input) const
 {
+    TraceRange trace_range("te.unpack_batch");
     const char *out = static_cast<const char *>(stage) + align_up(b.tables_bytes, 256);
     const double *res = reinterpret_cast<const double *>(out);
     const double *pv = res + b.n_results;
@@ -559,6 +562,7 @@ const char *te_last_error(void) { return g_last_error.c_str(); }
 
 te_status te_plan_create(const te_problem *pr, te_plan *out)
 {
+    TraceRange trace_range("te.plan_create");
     clear_error();
     if (!pr || !out)
         return fail(TE_ERR_INVALID, "null argument");

@@ -60,6 +60,7 @@ SearchConfig default_config(const DeviceInfo &dev, int d_y, int d_x, int k, int6
 // chunks of one (pair, point)) are never split.  Results do not depend on the split.
 te_status Plan::split_batches(size_t ws_bytes, std::vector<Batch> *out) const
 {
+    TraceRange trace_range("te.split_batches");
     const int G = p.n_pairs * p.n_points;
     std::vector<int> cur;
     for (int g = 0; g < G; ++g) {
@@ -89,6 +90,7 @@ te_status Plan::run_surrogates(const float *x, const float *y, const int32_t *pe
                                hipStream_t st, bool use_graph, double *te_orig, double *te_surr,
                                double *p_value) const
 {
+    TraceRange trace_range("te.surrogates");
     if (ws_bytes < min_bytes)
         return fail(TE_ERR_NOMEM, "workspace %zu bytes < minimum %zu", ws_bytes, min_bytes);
     hipError_t e;
@@ -100,6 +102,7 @@ te_status Plan::run_surrogates(const float *x, const float *y, const int32_t *pe
             if (g.x == x && g.y == y && g.perms == perms && g.ws == ws && g.stream == st && g.ws_bytes == ws_bytes)
                 ge = &g;
         if (!ge) {
+            TraceRange capture_range("te.graph_capture");
             GraphEntry ne;
             ne.x = x;
             ne.y = y;
@@ -150,8 +153,11 @@ te_status Plan::run_surrogates(const float *x, const float *y, const int32_t *pe
         }
         if ((e = hipGraphLaunch(ge->exec, st)) != hipSuccess)
             return hip_fail(e, "hipGraphLaunch");
-        if ((e = hipStreamSynchronize(st)) != hipSuccess)
-            return hip_fail(e, "hipStreamSynchronize");
+        {
+            TraceRange wait_range("te.wait");
+            if ((e = hipStreamSynchronize(st)) != hipSuccess)
+                return hip_fail(e, "hipStreamSynchronize");
+        }
         bool bad = false;
         for (size_t i = 0; i < ge->batches.size(); ++i)
             unpack_batch(ge->batches[i], ge->stages[i], te_orig, te_surr, p_value, &bad);
@@ -204,6 +210,7 @@ te_status Plan::run_surrogates(const float *x, const float *y, const int32_t *pe
 te_status Plan::run_surrogates_async(const float *x, const float *y, const int32_t *perms, char *ws,
                                      size_t ws_bytes, hipStream_t st, double *out) const
 {
+    TraceRange trace_range("te.surrogates_async");
     if (ws_bytes < full.total_bytes)
         return fail(TE_ERR_NOMEM, "te_surrogates_async needs the full workspace (%zu bytes), got %zu",
                     full.total_bytes, ws_bytes);
@@ -228,6 +235,7 @@ te_status Plan::run_surrogates_async(const float *x, const float *y, const int32
 te_status Plan::run_local(const float *x, const float *y, char *ws, size_t ws_bytes, hipStream_t st, double *lte,
                           double *te_out) const
 {
+    TraceRange trace_range("te.local");
     const int G = p.n_pairs * p.n_points;
     std::vector<int> all(G);
     std::iota(all.begin(), all.end(), 0);
@@ -307,6 +315,7 @@ te_status Plan::estimate_each(const float *x, const float *y, const int32_t *per
                               size_t ws_bytes, hipStream_t st, double *te_orig, double *te_surr,
                               double *p_value) const
 {
+    TraceRange trace_range("te.estimate_each");
     const PlainLayout L = plain_layout(n_surr);
     if (ws_bytes < L.total)
         return fail(TE_ERR_NOMEM, "workspace %zu bytes < plain-path size %zu", ws_bytes, L.total);
@@ -486,6 +495,7 @@ te_status te_knn_counts(const float *pts, int64_t dim_stride, const int64_t *off
                         int32_t d_x, int32_t k, void *ws_, size_t ws_bytes, void *hip_stream, float *eps,
                         int32_t *counts, double *te_out)
 {
+    TraceRange trace_range("te.knn_counts");
     clear_error();
     if (!ws_)
         return fail(TE_ERR_INVALID, "null argument");

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <memory>
 #include <mutex>
@@ -12,6 +13,16 @@
 #include "te_internal.h"
 
 namespace te {
+
+// A rocTX range over a host phase of the scheduler (planning, batch layout, enqueue,
+// graph capture, serving admission and steps, tuning): shown by `rocprofv3
+// --marker-trace`, a no-op without a profiler attached.  Ranges nest per thread.
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 te_status fail(te_status st, const char *fmt, ...);
 te_status hip_fail(hipError_t e, const char *what);

@@ -60,6 +60,7 @@ te_status Plan::run_scan(const float *x, const float *y, const int32_t *perms, c
                          char *ws, size_t ws_bytes, hipStream_t st, double *te_scan, int32_t *u_best,
                          double *te_surr, double *p_value) const
 {
+    TraceRange trace_range("te.delay_scan");
     const int G = p.n_pairs * p.n_points;
     const int n_u = (int)delays.size();
     const int S = p.n_surrogates;

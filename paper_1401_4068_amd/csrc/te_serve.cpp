@@ -371,6 +371,7 @@ void Server::drain_streams(const KernelClass *kc)
 // Copy the series in, upload the job's tables, embed every chunk once.
 bool Server::admit_one(Job *j)
 {
+    TraceRange trace_range("te.serve.admit");
     size_t off = 0;
     if (!ensure_tables(classes[j->cls]))
         return false;
@@ -473,6 +474,7 @@ void Server::poll_setup()
 // One search launch for class ci over blocks of ready jobs, FIFO, up to the pair budget.
 bool Server::issue_step(int ci)
 {
+    TraceRange trace_range("te.serve.step");
     KernelClass &kc = classes[ci];
     std::vector<ChunkDesc> tab;          // chunk descriptors of the step's pieces
     std::vector<ChunkDesc> leaders;      // first descriptor of each piece, n scaled by its chunks (queue costs)
@@ -650,6 +652,7 @@ bool Server::issue_step(int ci)
 
 void Server::finish(Job *j)
 {
+    TraceRange trace_range("te.serve.finish");
     const Batch &b = j->batch;
     const te_problem &p = j->plan->impl.p;
     const int G = p.n_pairs * p.n_points;

@@ -93,6 +93,7 @@ te_status te_autotune(int32_t d_y, int32_t d_x, int32_t k, int32_t n_points, int
                       size_t ws_bytes, void *hip_stream, int32_t *slots, int32_t *waves_per_wg,
                       int32_t *wg_per_cu, double *best_ms)
 {
+    TraceRange trace_range("te.autotune");
     clear_error();
     if (d_y < 1 || d_y > kMaxDimY || d_x < 1 || d_x > kMaxDimX || k < 1 || k > kMaxK || n_points <= k ||
         n_chunks < 1 || !ws_)
@@ -280,6 +281,7 @@ te_status te_plan_autotune(te_plan plan, const float *x, const float *y, const i
                            size_t ws_bytes, void *hip_stream, int32_t *slots, int32_t *waves_per_wg,
                            int32_t *wg_per_cu, double *best_ms)
 {
+    TraceRange trace_range("te.plan_autotune");
     clear_error();
     if (!plan || !x || !y || !ws_)
         return fail(TE_ERR_INVALID, "null argument");

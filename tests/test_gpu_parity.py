@@ -109,6 +109,13 @@ def test_knn_counts_large_chunk_multi_tile(te):
     _knn_case(te, [4100, 2500, 33], 3, 3, 4, "gauss", seed=5)
 
 
+@pytest.mark.parametrize("kind", ["grid", "dups"])
+def test_knn_counts_tiled_walk_with_ties(te, kind):
+    """Chunks of at least 8 192 points (pass 1 walks outward in tiles) on grid and
+    duplicated points, where distances tie everywhere."""
+    _knn_case(te, [8192, 9001], 3, 3, 4, kind, seed=7)
+
+
 # ------------------------------------------------------------ full estimates
 
 def _compare(wl, te_orig, te_surr=None, pv=None, points=None):
@@ -625,6 +632,22 @@ def test_chunk_sets_equal_single_chunk_search(te, monkeypatch, d_y, d_x, S):
     wl = synth.generic((6061, d_y, d_x, S), R=60, T=70, d_y=d_y, d_x=d_x, starts=(30, 41, 55),
                        windows=(13, 7, 10), trials=(60, 47, 33), n_surrogates=S)
     say("sets case", dict(d_y=d_y, d_x=d_x, S=S, sizes=wl.chunk_sizes().tolist()))
+    x, y, perms = dev(wl)
+    got = _both_ways(te, monkeypatch, wl, lambda plan: plan.surrogates(x, y, perms))
+    _compare(wl, *got)
+
+
+@pytest.mark.parametrize("step", [0.25, 0.5])
+def test_chunk_sets_tiled_walk_with_ties(te, monkeypatch, step):
+    """Windows of 8 400 and 9 600 points (the tiled pass 1 of sorted chunks, the wide set
+    kernel at d_y = d_x = 3) on series rounded to a grid of the given step, so that
+    coordinate differences and distances tie: sets against the single-chunk search bit
+    for bit, and against the oracle."""
+    wl = synth.generic((6071, int(step * 4)), R=400, T=70, d_y=3, d_x=3, starts=(30, 40), windows=(21, 24),
+                       trials=(400, 400), n_surrogates=3)
+    wl.x = (np.round(wl.x / step) * step).astype(np.float32)
+    wl.y = (np.round(wl.y / step) * step).astype(np.float32)
+    say("tied sets case", dict(step=step, sizes=wl.chunk_sizes().tolist()))
     x, y, perms = dev(wl)
     got = _both_ways(te, monkeypatch, wl, lambda plan: plan.surrogates(x, y, perms))
     _compare(wl, *got)

@@ -265,6 +265,38 @@ te_status te_knn_counts_noalloc(const float *pts, int64_t dim_stride, const int6
                                 int32_t n_chunks, int32_t d_y, int32_t d_x, int32_t k, void *hip_stream,
                                 float *eps, int32_t *counts, double *te_out);
 
+/* ------------------------------------------------------ embedding choice
+ * Local-predictor score of candidate embeddings (d_c, tau_c) of the target: the
+ * embedding section chooses the target's embedding dimension and delay as the
+ * pair whose past state best predicts the next sample with a local predictor
+ * (Ragwitz and Kantz; the paper gives no formula).  For candidate c the points
+ * are all trials r < n_trials and times t in [window_start, window_start +
+ * window_len), pooled trial-major (point r * window_len + (t - window_start)),
+ * with state (y_{t-1}, y_{t-1-tau_c}, ..., y_{t-1-(d_c-1)tau_c}) and target y_t.
+ * Each point's prediction is the mean of the targets of its k nearest other
+ * points (maximum norm of the binary32 coordinate differences; equal distances
+ * ranked by point index; targets summed in fp64 in rank order), and
+ *   score[c] = sum_i (y_i - pred_i)^2 / sum_i (y_i - mean y)^2   (NaN if the
+ * targets are constant); the smallest score marks the chosen embedding.
+ *   y        device float32 [n_trials][n_samples], the target series
+ *   dims, taus  host int32 [n_cand]: 1 <= d_c <= TE_RAGWITZ_MAX_DIM, tau_c >= 1,
+ *            and window_start >= 1 + (d_c - 1) tau_c (the state's history)
+ *   k        1..TE_RAGWITZ_MAX_K, below the pooled point count N (N <= 2^27)
+ *   ws       device workspace of te_ragwitz_workspace_bytes(...) bytes
+ *   pred     device float64 [n_cand][N] per-point predictions, or NULL
+ *   score    host float64 [n_cand], written before the call returns
+ * The stream is synchronised before return.  TE_ERR_INVALID on bad geometry or
+ * a non-finite value in a state or target (score untouched); TE_ERR_NOMEM if the
+ * workspace is too small. */
+#define TE_RAGWITZ_MAX_DIM 8
+#define TE_RAGWITZ_MAX_K 16
+#define TE_RAGWITZ_MAX_CANDIDATES 64
+te_status te_ragwitz_workspace_bytes(int32_t n_trials, int32_t window_len, const int32_t *dims, int32_t n_cand,
+                                     size_t *bytes);
+te_status te_ragwitz(const float *y, int32_t n_trials, int32_t n_samples, int32_t window_start, int32_t window_len,
+                     const int32_t *dims, const int32_t *taus, int32_t n_cand, int32_t k, void *ws, size_t ws_bytes,
+                     void *hip_stream, double *pred, double *score);
+
 /* ------------------------------------------------------------------ serving
  * A server keeps admitted jobs resident in a caller-provided device arena and
  * batches their searches continuously: a server thread admits queued jobs in

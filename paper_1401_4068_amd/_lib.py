@@ -88,6 +88,9 @@ SIGNATURES = {
     "te_tune_clear": ([], _st),
     "te_knn_counts": ([_vp, _i64, ctypes.POINTER(_i64), _i32, _i32, _i32, _i32, _vp, _sz, _vp, _vp, _vp, _dp], _st),
     "te_knn_counts_noalloc": ([_vp, _i64, ctypes.POINTER(_i64), _i32, _i32, _i32, _i32, _vp, _vp, _vp, _dp], _st),
+    "te_ragwitz_workspace_bytes": ([_i32, _i32, ctypes.POINTER(_i32), _i32, _szp], _st),
+    "te_ragwitz": ([_vp, _i32, _i32, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), _i32, _i32, _vp, _sz, _vp,
+                    _vp, _dp], _st),
 }
 
 # TE_NOALLOC_SCRATCH_BYTES of te.h: the static scratch of te_knn_counts_noalloc, per device

@@ -418,6 +418,34 @@ def knn_counts_noalloc(pts, offsets, d_y, d_x, k, eps, counts, stream=None, want
     return te
 
 
+def ragwitz(y, window_start, window_len, candidates, k, stream=None, ws=None, want_pred=False):
+    """Local-predictor scores of candidate target embeddings (te_ragwitz).
+
+    y: CUDA float32 [n_trials, n_samples]; candidates: sequence of (d, tau).  Returns
+    (scores float64 [n_cand] (the smallest marks the chosen embedding), predictions CUDA
+    float64 [n_cand, n_trials * window_len] or None)."""
+    torch = _torch()
+    if y.dim() != 2:
+        raise ValueError("y must be [n_trials, n_samples]")
+    dims = np.ascontiguousarray([int(d) for d, _ in candidates], np.int32)
+    taus = np.ascontiguousarray([int(t) for _, t in candidates], np.int32)
+    R, T = int(y.shape[0]), int(y.shape[1])
+    n = len(dims)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    if ws is None:
+        need = ctypes.c_size_t()
+        check(lib().te_ragwitz_workspace_bytes(R, window_len, dims.ctypes.data_as(i32p), n, ctypes.byref(need)))
+        ws = torch.empty(need.value, dtype=torch.uint8, device=y.device)
+    pred = torch.empty((n, R * window_len), dtype=torch.float64, device=y.device) if want_pred else None
+    scores = np.empty(n, np.float64)
+    sh, _ = _stream_handle(stream)
+    check(lib().te_ragwitz(_dev_ptr(y, torch.float32, "y"), R, T, window_start, window_len,
+                           dims.ctypes.data_as(i32p), taus.ctypes.data_as(i32p), n, k,
+                           _dev_ptr(ws, torch.uint8, "ws"), ws.numel(), sh,
+                           ctypes.c_void_p(pred.data_ptr()) if want_pred else None, _dp(scores)))
+    return scores, pred
+
+
 def autotune(d_y, d_x, k, n_points, n_chunks=None, stream=None):
     """Time every search launch shape on synthetic chunks (te_autotune); the winner is
     used by plans created afterwards.  Returns the chosen shape and its time."""

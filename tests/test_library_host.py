@@ -174,3 +174,29 @@ def test_drawn_permutation_sizes_and_checks_without_gpu():
     assert L.te_plan_permutations(p._h, ctypes.c_void_p(1 << 20), nb - 1, null, ctypes.c_void_p(1 << 20)) == 2
     q = _plan(n_surrogates=0)
     assert L.te_plan_permutations(q._h, ctypes.c_void_p(1 << 20), 256, null, ctypes.c_void_p(1 << 20)) == 0
+
+
+@pytest.mark.parametrize("dims,taus,k,w,W,msg", [
+    ([9], [1], 4, 20, 10, "candidate 0"),            # d above 8
+    ([2], [0], 4, 20, 10, "candidate 0"),            # tau below 1
+    ([3], [4], 4, 8, 10, "history"),                 # needs 1 + 2 * 4 = 9 samples before the window
+    ([1], [1], 0, 20, 10, "k must be"),
+    ([1], [1], 17, 20, 10, "k must be"),
+    ([1], [1], 4, 45, 10, "runs past"),
+    ([1], [1], 4, 20, 1, "points"),                  # N = 2 trials x 1 <= k
+    ([], [], 4, 20, 10, "n_cand"),
+])
+def test_ragwitz_rejects_invalid_geometry_without_gpu(dims, taus, k, w, W, msg):
+    """Validation happens before any device call (fake device pointers are never used)."""
+    from paper_1401_4068_amd import TEError
+    from paper_1401_4068_amd._lib import check
+    L = _lib_or_build().lib()
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    d = np.array(dims + [1], np.int32)
+    t = np.array(taus + [1], np.int32)
+    score = np.zeros(4)
+    with pytest.raises(TEError) as ei:
+        check(L.te_ragwitz(ctypes.c_void_p(16), 2, 50, w, W, d.ctypes.data_as(i32p), t.ctypes.data_as(i32p),
+                           len(dims), k, ctypes.c_void_p(256), 1 << 20, None, None,
+                           score.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    assert ei.value.status == 1 and msg in str(ei.value)

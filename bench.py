@@ -646,13 +646,91 @@ def served_record(args):
     return rec
 
 
+def ragwitz_record(args):
+    """Choice of the target embedding by the local-predictor score (te_ragwitz) on one
+    window of AR scenario 1's target (50 trials x 300 samples: N = 15 000 pooled points),
+    candidates d = 1..6 x tau = 1..2, k = 4.  One step scores every candidate."""
+    import torch
+    import synth
+    import paper_1401_4068_amd as te
+
+    wl = synth.ar_scenarios(1)
+    y = torch.from_numpy(np.ascontiguousarray(wl.y[0])).cuda()
+    w, W, k = int(wl.window_start[0]), int(wl.window_len[0]), 4
+    cands = [(d, tau) for tau in (1, 2) for d in range(1, 7)]
+    R = int(y.shape[0])
+    N = R * W
+    dims = np.array([d for d, _ in cands], np.int32)
+    import ctypes
+    need = ctypes.c_size_t()
+    te._lib.check(te.lib().te_ragwitz_workspace_bytes(R, W, dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                                      len(cands), ctypes.byref(need)))
+    ws = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+    for _ in range(args.warmup):
+        te.ragwitz(y, w, W, cands, k, ws=ws)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        scores, _ = te.ragwitz(y, w, W, cands, k, ws=ws)
+    ev1.record()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    dev_ms = ev0.elapsed_time(ev1) / args.steps
+    # executed FP32 operations: per (reference, candidate point) pair d subtractions, d - 1
+    # maxes and one min or compare (abs is an operand modifier)
+    ops = sum(2 * d for d, _ in cands) * float(N) * float(N)
+    achieved = ops / (dev_ms * 1e-3) / 1e12
+    peak = FP32_LANE_INSTR_PER_S / 1e12
+    best = int(np.argmin(scores))
+    rec = dict(
+        metric="embedding candidates scored/s (local-predictor error, k nearest of all pooled points)",
+        value=round(len(cands) * args.steps / dt, 2), unit="candidates/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(dt / args.steps * 1e3, 4), higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f32", data="synthetic",
+        config=dict(workload="ragwitz_ar_scenario1_window", trials=R, window=[w, w + W], points=N,
+                    candidates=[list(c) for c in cands], k=k, workspace_bytes=int(need.value),
+                    path="te_ragwitz (synchronous)"),
+        distance_evals_per_s=round(len(cands) * N * (N - 1) * args.steps / dt, 1),
+        roofline=dict(bound="alu", achieved=round(achieved, 3), peak=round(peak, 3), unit="TFLOP/s",
+                      frac=round(achieved / peak, 4), traffic=None,
+                      peak_derivation="78.64e12 FP32 lane-instr/s (256 CU x 4 SIMD x 32 lanes x 2.4 GHz), one "
+                                      "executed op per instruction",
+                      kernel="rag_knn_kernel<d> (+ embed, score)", device_ms_per_step=round(dev_ms, 4),
+                      ops_per_step=ops),
+        findings=dict(scores=[round(float(v), 6) for v in scores], chosen=list(cands[best])))
+    if not args.no_cpu:
+        from oracle import ragwitz as rg
+        from synth.rng import derive_key, permutation
+        yh = np.ascontiguousarray(wl.y[0])
+        done, t_cpu = 0, 0.0
+        order = permutation(derive_key(4069, N), N)
+        prep = {}
+        while t_cpu < 10.0 and done < N:
+            idx = order[done:done + 25]
+            t1 = time.perf_counter()
+            for d, tau in cands:
+                if (d, tau) not in prep:
+                    prep[(d, tau)] = rg.states(yh, d, tau, w, W)
+                S, tgt = prep[(d, tau)]
+                rg.predictions_points(S, tgt, k, idx)
+            t_cpu += time.perf_counter() - t1
+            done += len(idx)
+        rec["cpu_baseline"] = dict(value=len(cands) * done / N / t_cpu, unit="candidates/s", cores=1, kind="oracle",
+                                   sample="%d of %d points' predictions for each of the %d candidates (numpy, one "
+                                          "thread), %.1f s; scaled by points" % (done, N, len(cands), t_cpu))
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uneven",
-                    choices=["uneven", "nonlinear", "linear", "meg", "served", "ar0", "ar1", "ar2", "ar3"],
+                    choices=["uneven", "nonlinear", "linear", "meg", "served", "ar0", "ar1", "ar2", "ar3",
+                             "ragwitz"],
                     help="uneven: batched surrogates (60 time points x 201 chunks of 1 000-49 400 points); "
                          "ar0: delay recovery against the amount of data; ar1-ar3: the AR coupling scenarios")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -693,6 +771,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "served":
         rec = served_record(args)
+    elif args.workload == "ragwitz":
+        rec = ragwitz_record(args)
     elif args.workload.startswith("ar"):
         rec = scan_record(args, int(args.workload[2:]))
     else:

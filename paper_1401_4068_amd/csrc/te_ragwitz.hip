@@ -8,6 +8,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -61,38 +62,32 @@ __global__ void rag_embed_kernel(const float *__restrict__ y, int T, int w, int 
         atomicOr(bad, 1);
 }
 
-// One wave per 64 reference points (lane = reference), candidates uniform in index
-// order, eight at a time on scalar loads.  The list (bd, bi) holds the k smallest
-// (distance, index) pairs seen so far, ascending; a candidate enters only if strictly
-// closer than the k-th, so among equal distances the smaller index stays ahead.
-template <int D>
-__global__ void __launch_bounds__(64) rag_knn_kernel(const float *__restrict__ rows, const float *__restrict__ tgt,
-                                                     int N, int k, double *__restrict__ pred,
-                                                     double *__restrict__ sq)
-{
-    const int lane = (int)threadIdx.x;
-    const int i = (int)blockIdx.x * kWave + lane;
-    const bool valid = i < N;
-    const int ii = valid ? i : N - 1;
-    float ref[D];
+// The k smallest (distance, index) pairs seen so far, ascending.  Entries arrive with
+// an index above every listed entry of equal distance, so inserting only what is
+// strictly closer than the k-th keeps equal distances in index order.
+template <int KC>                                 // capacity: k <= KC
+struct TopK {
+    float bd[KC];
+    int bi[KC];
+    float thr;                                    // bd[k - 1]
+    int k;
+    __device__ void init(int k_)
+    {
+        thr = __builtin_inff();
+        k = k_;
 #pragma unroll
-    for (int m = 0; m < D; ++m)
-        ref[m] = rows[(int64_t)m * N + ii];
-    float bd[kRagMaxK];
-    int bi[kRagMaxK];
-#pragma unroll
-    for (int p = 0; p < kRagMaxK; ++p) {
-        bd[p] = __builtin_inff();
-        bi[p] = 0;
+        for (int p = 0; p < KC; ++p) {
+            bd[p] = __builtin_inff();
+            bi[p] = 0;
+        }
     }
-    float thr = __builtin_inff();                 // bd[k - 1]
-    // (x, j) with x < bd[k - 1] and j above every listed index: entries larger than x
-    // move down one place and x goes behind the last entry <= x, so equal distances
-    // stay in index order (from the last place up, each place reads the one above
-    // before that one changes)
-    auto insert = [&](float x, int j) {
+    // (x, j) with x < thr: entries larger than x move down one place and x goes behind
+    // the last entry <= x (from the last place up, each place reads the one above before
+    // that one changes)
+    __device__ __forceinline__ void insert(float x, int j)
+    {
 #pragma unroll
-        for (int p = kRagMaxK - 1; p >= 1; --p) {
+        for (int p = KC - 1; p >= 1; --p) {
             if (p < k) {
                 const bool move = bd[p - 1] > x;
                 const bool put = !move && bd[p] > x;
@@ -105,12 +100,45 @@ __global__ void __launch_bounds__(64) rag_knn_kernel(const float *__restrict__ r
             bi[0] = j;
         }
 #pragma unroll
-        for (int p = 0; p < kRagMaxK; ++p)
+        for (int p = 0; p < KC; ++p)
             if (p == k - 1)
                 thr = bd[p];
-    };
-    int j = 0;
-    for (; j + 8 <= N; j += 8) {
+    }
+};
+
+// One wave per (64 RPL reference points, candidate segment): lane l holds references
+// b + l + 64 r (r < RPL), the segment's candidates are uniform in index order, eight at
+// a time on scalar loads, so each load feeds 8 RPL distances per lane.  The segment's
+// list of each reference goes to lst_d / lst_i [segment][place][point] (places a
+// segment cannot fill stay at distance +inf).  Four references per lane while their
+// lists fit in registers (capacity up to 8), one for lists of 16.
+constexpr int refs_per_lane(int kc) { return kc <= 8 ? 4 : 1; }
+
+template <int D, int KC>
+__global__ void __launch_bounds__(64) rag_knn_kernel(const float *__restrict__ rows, int N, int k, int seg_len,
+                                                     float *__restrict__ lst_d, int *__restrict__ lst_i)
+{
+    constexpr int RPL = refs_per_lane(KC);
+    const int lane = (int)threadIdx.x;
+    const int seg = (int)blockIdx.y;
+    const int j0 = seg * seg_len;
+    const int j1 = min(N, j0 + seg_len);
+    int ri[RPL];
+    float ref[RPL][D];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        ri[r] = (int)blockIdx.x * (kWave * RPL) + r * kWave + lane;
+        const int ii = ri[r] < N ? ri[r] : N - 1;
+#pragma unroll
+        for (int m = 0; m < D; ++m)
+            ref[r][m] = rows[(int64_t)m * N + ii];
+    }
+    TopK<KC> L[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r)
+        L[r].init(k);
+    int j = j0;
+    for (; j + 8 <= j1; j += 8) {
         float c[8][D];
 #pragma unroll
         for (int m = 0; m < D; ++m) {
@@ -119,45 +147,94 @@ __global__ void __launch_bounds__(64) rag_knn_kernel(const float *__restrict__ r
             for (int u = 0; u < 8; ++u)
                 c[u][m] = v[u];
         }
-        float dist[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            float dm = __builtin_fabsf(c[u][0] - ref[0]);
+        for (int r = 0; r < RPL; ++r) {
+            float dist[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                float dm = __builtin_fabsf(c[u][0] - ref[r][0]);
+#pragma unroll
+                for (int m = 1; m < D; ++m)
+                    dm = fmaxf(dm, __builtin_fabsf(c[u][m] - ref[r][m]));
+                dist[u] = (j + u == ri[r]) ? __builtin_inff() : dm;
+            }
+            const float mn = fminf(fminf(fminf(dist[0], dist[1]), fminf(dist[2], dist[3])),
+                                   fminf(fminf(dist[4], dist[5]), fminf(dist[6], dist[7])));
+            if (__builtin_amdgcn_ballot_w64(mn < L[r].thr)) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (dist[u] < L[r].thr)
+                        L[r].insert(dist[u], j + u);
+            }
+        }
+    }
+    for (; j < j1; ++j) {
+        float cj[D];
+#pragma unroll
+        for (int m = 0; m < D; ++m)
+            cj[m] = sload(rows + (int64_t)m * N + j);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            float dm = __builtin_fabsf(cj[0] - ref[r][0]);
 #pragma unroll
             for (int m = 1; m < D; ++m)
-                dm = fmaxf(dm, __builtin_fabsf(c[u][m] - ref[m]));
-            dist[u] = (j + u == i) ? __builtin_inff() : dm;
-        }
-        const float mn = fminf(fminf(fminf(dist[0], dist[1]), fminf(dist[2], dist[3])),
-                               fminf(fminf(dist[4], dist[5]), fminf(dist[6], dist[7])));
-        if (__builtin_amdgcn_ballot_w64(mn < thr)) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (dist[u] < thr)
-                    insert(dist[u], j + u);
+                dm = fmaxf(dm, __builtin_fabsf(cj[m] - ref[r][m]));
+            if (j != ri[r] && dm < L[r].thr)
+                L[r].insert(dm, j);
         }
     }
-    for (; j < N; ++j) {
-        float dm = __builtin_fabsf(sload(rows + j) - ref[0]);
 #pragma unroll
-        for (int m = 1; m < D; ++m)
-            dm = fmaxf(dm, __builtin_fabsf(sload(rows + (int64_t)m * N + j) - ref[m]));
-        if (j != i && dm < thr)
-            insert(dm, j);
+    for (int r = 0; r < RPL; ++r)
+        if (ri[r] < N) {
+#pragma unroll
+            for (int p = 0; p < KC; ++p)
+                if (p < k) {
+                    const int64_t o = ((int64_t)seg * k + p) * N + ri[r];
+                    lst_d[o] = L[r].bd[p];
+                    lst_i[o] = L[r].bi[p];
+                }
+        }
+}
+
+// Thread = point: the segments' lists merged in segment order (indices ascend across
+// segments and within a list equal distances ascend in index, so the strict insertion
+// keeps the rank order), then the prediction -- the neighbours' targets summed in rank
+// order in fp64 -- and its squared error.
+template <int KC>
+__global__ void __launch_bounds__(256) rag_merge_kernel(const float *__restrict__ lst_d,
+                                                        const int *__restrict__ lst_i,
+                                                        const float *__restrict__ tgt, int N, int k, int n_seg,
+                                                        double *__restrict__ pred, double *__restrict__ sq)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= N)
+        return;
+    TopK<KC> L;
+    L.init(k);
+    for (int seg = 0; seg < n_seg; ++seg) {
+        float xd[KC];
+        int xi[KC];
+#pragma unroll
+        for (int p = 0; p < KC; ++p) {            // the segment's list, all loads in flight
+            const int64_t o = ((int64_t)seg * k + (p < k ? p : 0)) * N + i;
+            xd[p] = p < k ? lst_d[o] : __builtin_inff();
+            xi[p] = p < k ? lst_i[o] : 0;
+        }
+#pragma unroll
+        for (int p = 0; p < KC; ++p)
+            if (xd[p] < L.thr)
+                L.insert(xd[p], xi[p]);
     }
-    // the prediction: neighbour targets summed in rank order in fp64
     double s = 0.0;
 #pragma unroll
-    for (int p = 0; p < kRagMaxK; ++p)
+    for (int p = 0; p < KC; ++p)
         if (p < k)
-            s += (double)tgt[bi[p]];
+            s += (double)tgt[L.bi[p]];
     const double yhat = s / (double)k;
-    if (valid) {
-        if (pred != nullptr)
-            pred[i] = yhat;
-        const double e = (double)tgt[i] - yhat;
-        sq[i] = e * e;
-    }
+    if (pred != nullptr)
+        pred[i] = yhat;
+    const double e = (double)tgt[i] - yhat;
+    sq[i] = e * e;
 }
 
 // Fixed-order sum over a workgroup of kScoreThreads threads.
@@ -200,28 +277,76 @@ __global__ void __launch_bounds__(kScoreThreads) rag_score_kernel(const float *_
         score[c] = V > 0.0 ? E / V : __builtin_nan("");
 }
 
-hipError_t launch_knn(int d, const float *rows, const float *tgt, int N, int k, double *pred, double *sq,
-                      hipStream_t st)
+// Candidate segments per point: enough (wave, segment) pairs to give every SIMD of the
+// chip several waves (a wave holds 64 rpl references), segments of at least 64 points
+// (a multiple of 8), at most 64.
+struct Segments {
+    int len = 0, n = 0;
+};
+
+Segments segments(int64_t N, int rpl)
 {
-    const dim3 grid((unsigned)((N + kWave - 1) / kWave)), block(kWave);
+    const int64_t blocks = (N + kWave * rpl - 1) / (kWave * rpl);
+    int64_t want = (16384 + blocks - 1) / blocks;
+    want = want < 1 ? 1 : (want > 64 ? 64 : want);
+    int64_t len = (N + want - 1) / want;
+    len = len < 64 ? 64 : (len + 7) / 8 * 8;
+    Segments s;
+    s.len = (int)len;
+    s.n = (int)((N + len - 1) / len);
+    return s;
+}
+
+template <int KC>
+hipError_t launch_knn_kc(int d, const float *rows, int N, int k, const Segments &sg, float *lst_d, int *lst_i,
+                         hipStream_t st)
+{
+    constexpr int RPL = refs_per_lane(KC);
+    const dim3 grid((unsigned)((N + kWave * RPL - 1) / (kWave * RPL)), (unsigned)sg.n);
+    const dim3 block(kWave);
     switch (d) {
-    case 1: rag_knn_kernel<1><<<grid, block, 0, st>>>(rows, tgt, N, k, pred, sq); break;
-    case 2: rag_knn_kernel<2><<<grid, block, 0, st>>>(rows, tgt, N, k, pred, sq); break;
-    case 3: rag_knn_kernel<3><<<grid, block, 0, st>>>(rows, tgt, N, k, pred, sq); break;
-    case 4: rag_knn_kernel<4><<<grid, block, 0, st>>>(rows, tgt, N, k, pred, sq); break;
-    case 5: rag_knn_kernel<5><<<grid, block, 0, st>>>(rows, tgt, N, k, pred, sq); break;
-    case 6: rag_knn_kernel<6><<<grid, block, 0, st>>>(rows, tgt, N, k, pred, sq); break;
-    case 7: rag_knn_kernel<7><<<grid, block, 0, st>>>(rows, tgt, N, k, pred, sq); break;
-    case 8: rag_knn_kernel<8><<<grid, block, 0, st>>>(rows, tgt, N, k, pred, sq); break;
+    case 1: rag_knn_kernel<1, KC><<<grid, block, 0, st>>>(rows, N, k, sg.len, lst_d, lst_i); break;
+    case 2: rag_knn_kernel<2, KC><<<grid, block, 0, st>>>(rows, N, k, sg.len, lst_d, lst_i); break;
+    case 3: rag_knn_kernel<3, KC><<<grid, block, 0, st>>>(rows, N, k, sg.len, lst_d, lst_i); break;
+    case 4: rag_knn_kernel<4, KC><<<grid, block, 0, st>>>(rows, N, k, sg.len, lst_d, lst_i); break;
+    case 5: rag_knn_kernel<5, KC><<<grid, block, 0, st>>>(rows, N, k, sg.len, lst_d, lst_i); break;
+    case 6: rag_knn_kernel<6, KC><<<grid, block, 0, st>>>(rows, N, k, sg.len, lst_d, lst_i); break;
+    case 7: rag_knn_kernel<7, KC><<<grid, block, 0, st>>>(rows, N, k, sg.len, lst_d, lst_i); break;
+    case 8: rag_knn_kernel<8, KC><<<grid, block, 0, st>>>(rows, N, k, sg.len, lst_d, lst_i); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+template <int KC>
+hipError_t launch_candidate(int d, const float *rows, const float *tgt, int N, int k, const Segments &sg,
+                            float *lst_d, int *lst_i, double *pred, double *sq, hipStream_t st)
+{
+    hipError_t e = launch_knn_kc<KC>(d, rows, N, k, sg, lst_d, lst_i, st);
+    if (e != hipSuccess)
+        return e;
+    rag_merge_kernel<KC><<<dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st>>>(lst_d, lst_i, tgt, N, k, sg.n,
+                                                                                 pred, sq);
+    return hipGetLastError();
+}
+
+// the k nearest of each point for one candidate, merged, with its predictions: the list
+// capacity is the smallest of 4, 8, 16 that holds k
+hipError_t launch_knn(int d, const float *rows, const float *tgt, int N, int k, float *lst_d, int *lst_i,
+                      double *pred, double *sq, hipStream_t st)
+{
+    if (k <= 4)
+        return launch_candidate<4>(d, rows, tgt, N, k, segments(N, refs_per_lane(4)), lst_d, lst_i, pred, sq, st);
+    if (k <= 8)
+        return launch_candidate<8>(d, rows, tgt, N, k, segments(N, refs_per_lane(8)), lst_d, lst_i, pred, sq, st);
+    return launch_candidate<16>(d, rows, tgt, N, k, segments(N, refs_per_lane(16)), lst_d, lst_i, pred, sq, st);
+}
+
 // Workspace layout: flag | targets [N] | states of each candidate [d_c][N] | squared errors
-// [n_cand][N] | scores [n_cand], each part 256-byte aligned.
+// [n_cand][N] | scores [n_cand] | segment lists (distances, indices) [segments][k][N] for
+// k up to TE_RAGWITZ_MAX_K, reused by every candidate; each part 256-byte aligned.
 struct RagLayout {
-    size_t flag = 0, tgt = 0, sq = 0, score = 0, total = 0;
+    size_t flag = 0, tgt = 0, sq = 0, score = 0, lst_d = 0, lst_i = 0, total = 0;
     std::vector<size_t> rows;
 };
 
@@ -239,6 +364,12 @@ RagLayout rag_layout(int64_t N, const int32_t *dims, int n_cand)
     o += align_up(sizeof(double) * (size_t)N * (size_t)n_cand, 256);
     L.score = o;
     o += align_up(sizeof(double) * (size_t)n_cand, 256);
+    const int n_seg = std::max(segments(N, refs_per_lane(8)).n, segments(N, refs_per_lane(16)).n);
+    const size_t lst = (size_t)n_seg * (size_t)kRagMaxK * (size_t)N;
+    L.lst_d = o;
+    o += align_up(sizeof(float) * lst, 256);
+    L.lst_i = o;
+    o += align_up(sizeof(int) * lst, 256);
     L.total = o;
     return L;
 }
@@ -326,11 +457,13 @@ te_status te_ragwitz(const float *y, int32_t n_trials, int32_t n_samples, int32_
         if ((e = hipGetLastError()) != hipSuccess)
             return hip_fail(e, "rag_embed_kernel");
     }
+    float *lst_d = reinterpret_cast<float *>(ws + L.lst_d);
+    int *lst_i = reinterpret_cast<int *>(ws + L.lst_i);
     for (int c = 0; c < n_cand; ++c) {
         const float *rows = reinterpret_cast<const float *>(ws + L.rows[c]);
-        if ((e = launch_knn(dims[c], rows, tgt, N, k, pred ? pred + (int64_t)c * N : nullptr, sq + (int64_t)c * N,
-                            st)) != hipSuccess)
-            return hip_fail(e, "rag_knn_kernel");
+        if ((e = launch_knn(dims[c], rows, tgt, N, k, lst_d, lst_i, pred ? pred + (int64_t)c * N : nullptr,
+                            sq + (int64_t)c * N, st)) != hipSuccess)
+            return hip_fail(e, "rag_knn_kernel / rag_merge_kernel");
     }
     rag_score_kernel<<<dim3((unsigned)n_cand), dim3(kScoreThreads), 0, st>>>(tgt, sq, N, dscore);
     if ((e = hipGetLastError()) != hipSuccess)

@@ -59,7 +59,7 @@ def _check(te, y, w, W, cands, k, full=True, sample=None):
     return scores
 
 
-@pytest.mark.parametrize("k", [1, 4, 16])
+@pytest.mark.parametrize("k", [1, 4, 7, 16])
 def test_small_windows_bit_exact(te, k):
     y = _ar_series(1, 30, 60)
     _check(te, y, 17, 40, [(1, 1), (2, 1), (2, 2), (3, 1), (4, 2), (8, 2)], k)

@@ -211,6 +211,7 @@ __global__ void __launch_bounds__(256) rag_merge_kernel(const float *__restrict_
         return;
     TopK<KC> L;
     L.init(k);
+#pragma unroll 4
     for (int seg = 0; seg < n_seg; ++seg) {
         float xd[KC];
         int xi[KC];
